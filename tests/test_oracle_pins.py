@@ -1,0 +1,361 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks a closed form, an
+invariant, a library routine or a brute-force/independent computation, chosen
+so that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them. Paper passages: Sec. III (lifting,
+Eqs. numdens/numAtoms/Tcontribution; restricting, Eq. stress), Sec. II.B
+(velocity-Verlet MD).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import oracle
+
+RC = 2.5
+
+
+def phi_ts(r, rc=RC):
+    """LJTS pair energy written from its textbook definition (test-side)."""
+    r = np.asarray(r, dtype=float)
+    lj = 4.0 * (r ** -12 - r ** -6)
+    return np.where(r < rc, lj - 4.0 * (rc ** -12 - rc ** -6), 0.0)
+
+
+def fcc_shell_sum(rho, rc):
+    """E_cold / N of the infinite FCC lattice: 1/2 sum over R != 0, |R| < rc."""
+    l = (4.0 / rho) ** (1.0 / 3.0)
+    m = int(math.ceil(rc / l)) + 1
+    basis = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    g = np.arange(-m, m + 1)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1).astype(float)
+    R = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * l
+    r = np.sqrt((R ** 2).sum(axis=1))
+    r = r[(r > 1e-12) & (r < rc)]
+    return 0.5 * phi_ts(r, rc).sum()
+
+
+def two_atoms(r, L=20.0):
+    x = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+    return oracle.forces(x, L, RC)
+
+
+# --- pair potential special cases (LJTS closed forms) -----------------------
+
+def test_pair_potential_special_points():
+    shift = 4.0 * (RC ** -12 - RC ** -6)
+    # zero of the unshifted LJ at r = sigma
+    F, U, W = two_atoms(1.0)
+    assert U == pytest.approx(-shift, abs=1e-14)
+    # force on atom 0 points away from atom 1 (repulsive), 24 at r = sigma
+    assert F[0, 0] == pytest.approx(-24.0, rel=1e-14)
+    assert F[1, 0] == pytest.approx(24.0, rel=1e-14)
+    # minimum at 2^(1/6): force zero, depth -eps
+    rm = 2.0 ** (1.0 / 6.0)
+    F, U, W = two_atoms(rm)
+    assert abs(F[0, 0]) < 1e-12
+    assert U == pytest.approx(-1.0 - shift, rel=1e-13)
+    # just inside the cutoff: energy continuous (-> 0), force unshifted
+    F, U, W = two_atoms(RC * (1 - 1e-12))
+    assert abs(U) < 1e-12
+    f_rc = 24.0 * (2.0 * RC ** -13 - RC ** -7)
+    assert F[1, 0] == pytest.approx(f_rc, rel=1e-9)
+    # pair virial r.f
+    assert W == pytest.approx(RC * f_rc, rel=1e-9)
+    # at and beyond the cutoff: nothing (strict <)
+    for r in (RC, RC * 1.01):
+        F, U, W = two_atoms(r)
+        assert U == 0.0 and W == 0.0 and not F.any()
+
+
+# --- lifting geometry (Eqs. numdens, numAtoms) --------------------------------
+
+@pytest.mark.parametrize("n_c,rho", [(2, 0.5), (3, 1.2), (4, 0.8442), (5, 0.3)])
+def test_lattice_counts_and_density(n_c, rho):
+    x = oracle.lattice(n_c, rho)
+    N = 4 * n_c ** 3
+    L = oracle.box_length(n_c, rho)
+    assert x.shape == (N, 3)
+    assert rho * L ** 3 == pytest.approx(N, rel=1e-14)
+    assert (x >= 0).all() and (x < L).all()
+    # nearest-neighbour distance of FCC is l / sqrt(2), with 12 neighbours
+    l = oracle.lattice_param(rho)
+    d = x[None, :, :] - x[:, None, :]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    assert r.min() == pytest.approx(l / math.sqrt(2), rel=1e-12)
+    if n_c >= 3:
+        assert ((np.abs(r - l / math.sqrt(2)) < 1e-9).sum(axis=1) == 12).all()
+    # distinct sites
+    assert len({tuple(np.round(p, 9)) for p in x}) == N
+
+
+# --- P7: E_cold against independent shell enumeration --------------------------
+
+@pytest.mark.parametrize("n_c,rho,rc", [(4, 0.8442, 2.5), (5, 0.3, 2.5), (5, 1.1, 2.5), (4, 1.2, 3.0), (6, 0.9, 4.0)])
+def test_ecold_matches_fcc_shell_sum(n_c, rho, rc):
+    N = 4 * n_c ** 3
+    e_orc = oracle.ecold(n_c, rho, rc) / N
+    e_ref = fcc_shell_sum(rho, rc)
+    # the oracle's lattice is rounded to float (the device's storage precision);
+    # forces vanish on a perfect lattice, so the rounding moves E_cold only at
+    # second order in the ~1e-7 displacements: well below 1e-10 relative
+    assert e_orc == pytest.approx(e_ref, rel=1e-10, abs=1e-12)
+
+
+def test_ecold_is_size_independent():
+    vals = [oracle.ecold(n, 0.8442, 2.5) / (4 * n ** 3) for n in (3, 4, 5, 6)]
+    assert np.ptp(vals) < 1e-10
+
+
+# --- P8: T = 0 virial identity W / (3V) = -dE_cold/dV -------------------------
+
+@pytest.mark.parametrize("rho", [0.8442, 1.05, 0.62])
+def test_lattice_virial_is_minus_dE_dV(rho):
+    n_c, rc = 4, 2.5
+    N = 4 * n_c ** 3
+    x = oracle.lattice(n_c, rho)
+    L = oracle.box_length(n_c, rho)
+    V = L ** 3
+    _, _, W = oracle.forces(x, L, rc)
+    # E(V) per atom from the shell sum; rho = N / V
+    h = 1e-6 * V
+
+    def E(Vv):
+        return N * fcc_shell_sum(N / Vv, rc)
+
+    dEdV = (E(V + h) - E(V - h)) / (2 * h)
+    assert W / (3 * V) == pytest.approx(-dEdV, rel=2e-6)
+
+
+# --- P5: all pairs vs an independent cell list -------------------------------
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_all_pairs_equals_cell_list(seed):
+    n_c, rho = 6, 0.5
+    rng = np.random.default_rng(seed)
+    L = oracle.box_length(n_c, rho)
+    x = oracle.lattice(n_c, rho) + rng.normal(scale=0.15, size=(4 * n_c ** 3, 3))
+    x -= L * np.floor(x / L)
+    F1, U1, W1 = oracle.forces(x, L, RC)
+    F2, U2, W2 = oracle.forces_celllist(x, L, RC)
+    assert np.abs(F1 - F2).max() <= 1e-12 * np.abs(F1).max()
+    assert U1 == pytest.approx(U2, rel=1e-12)
+    assert W1 == pytest.approx(W2, rel=1e-12)
+
+
+# --- P12: multi-image box equals its 2x2x2 replica under minimum image ----------
+
+def test_multi_image_box_matches_replica():
+    n_c, rho, rc = 3, 1.2, 3.0
+    L = oracle.box_length(n_c, rho)
+    assert rc > L / 2 and rc < L
+    N = 4 * n_c ** 3
+    assert oracle.ecold(n_c, rho, rc) / N == pytest.approx(fcc_shell_sum(rho, rc), rel=1e-10)
+    rng = np.random.default_rng(3)
+    x = oracle.lattice(n_c, rho) + rng.normal(scale=0.05, size=(N, 3))
+    x -= L * np.floor(x / L)
+    F, U, W = oracle.forces(x, L, rc)
+    shifts = np.array([[a, b, c] for a in (0, 1) for b in (0, 1) for c in (0, 1)], dtype=float)
+    X = (x[None, :, :] + L * shifts[:, None, :]).reshape(-1, 3)
+    F8, U8, W8 = oracle.forces(X, 2 * L, rc)
+    assert rc <= L  # big box uses the minimum image
+    assert np.abs(F8[:N] - F).max() <= 1e-11 * np.abs(F).max()
+    assert U8 == pytest.approx(8 * U, rel=1e-12)
+    assert W8 == pytest.approx(8 * W, rel=1e-12)
+
+
+# --- P11: Philox4x64-10 equals numpy's Philox bitwise --------------------------
+
+@pytest.mark.parametrize("key,ctr", [((20250806, 0), (0, 0, 0, 0)), ((1, 2), (5, 0, 0, 0)),
+                                     ((2 ** 64 - 1, 12345), (3 * 3999 + 2, 0, 0, 0)),
+                                     ((7, 2 ** 63), (2 ** 40, 3, 9, 1))])
+def test_philox_matches_numpy(key, ctr):
+    mine = oracle.philox4x64_10(key, ctr)
+    # numpy's Philox increments its 256-bit counter before each block
+    c = list(ctr)
+    for i in range(4):
+        if c[i] > 0:
+            c[i] -= 1
+            break
+        c[i] = 2 ** 64 - 1
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    ref = np.array([bg.random_raw() for _ in range(4)], dtype=np.uint64)
+    assert (mine == ref).all()
+
+
+def test_gaussian_draws_are_standard_normal():
+    z = np.array([oracle.gauss(99, 3, a, c) for a in range(4000) for c in range(3)])
+    assert abs(z.mean()) < 4 / math.sqrt(z.size)
+    assert abs(z.var() - 1) < 4 * math.sqrt(2 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+
+
+def test_gaussian_box_muller_definition():
+    # first two Philox words -> Box-Muller, written out here from the textbook form
+    w = oracle.philox4x64_10((11, 4), (3 * 17 + 1, 0, 0, 0))
+    u1 = 1.0 - float(int(w[0]) >> 11) * 2.0 ** -53
+    u2 = float(int(w[1]) >> 11) * 2.0 ** -53
+    z = math.sqrt(-2 * math.log(u1)) * math.cos(2 * math.pi * u2)
+    assert oracle.gauss(11, 4, 17, 1) == pytest.approx(z, rel=1e-15, abs=1e-15)
+
+
+# --- P9: lifting invariants ---------------------------------------------------
+
+@pytest.mark.parametrize("n_c,rho,T", [(4, 0.8442, 0.722), (2, 0.3, 2.0), (5, 1.1, 3.0)])
+def test_lift_invariants(n_c, rho, T):
+    N = 4 * n_c ** 3
+    e = 1.5 * T * (1 - 1 / N)
+    cell = oracle.Cell(rho=rho, e=e, n_c=n_c, seed=5, cell_id=9)
+    x, v, Ec = oracle.lift(cell)
+    assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+    assert np.array_equal(v, v.astype(np.float32).astype(np.float64))
+    K = 0.5 * (v ** 2).sum()
+    assert K == pytest.approx(N * e, rel=1e-6)  # exact in FP64 before rounding to float
+    assert np.abs(v.sum(axis=0)).max() < 1e-5 * np.abs(v).sum()
+    # first-guess temperature 2E/N_DOF equals T when e = N_DOF T / (2N)
+    assert 2 * N * e / (3 * N - 3) == pytest.approx(T, rel=1e-14)
+    assert Ec == pytest.approx(oracle.ecold(n_c, rho, 2.5), rel=1e-15)
+
+
+def test_rescale_pins_energy_above_cold():
+    cell = oracle.Cell(rho=0.8442, e=1.0788, n_c=4, dt=0.005)
+    sch = oracle.Schedule(n_steps=300, n_avg=100, rescale_steps=(50, 150))
+    r = oracle.run(cell, sch)
+    for k in (50, 150):
+        assert (r.K[k] + r.U[k] - r.Ecold_total) / cell.N == pytest.approx(cell.e, rel=1e-12)
+    # between re-pins the energy is conserved (NVE), so the pin only corrects
+    # the small integration error
+    E = r.K + r.U - r.Ecold_total
+    assert np.abs(E[51:150] / cell.N - cell.e).max() < 1e-3
+
+
+def test_below_cold_flag():
+    # a target energy below the cold lattice after a disordering run: start hot,
+    # then demand e = 0 at a re-pin once E_pot > E_cold
+    cell = oracle.Cell(rho=0.8442, e=2.0, n_c=3, dt=0.005)
+    x, v, Ec = oracle.lift(cell)
+    cold = oracle.Cell(rho=0.8442, e=1e-9, n_c=3, dt=0.005)
+    r = oracle.run(cold, oracle.Schedule(n_steps=100, n_avg=50, rescale_steps=(60,)), x=x, v=v, Ecold_total=Ec)
+    assert r.result.status & oracle.BELOW_COLD
+
+
+# --- P1 / P2: Newton's third law and momentum ----------------------------------
+
+def test_newton3_and_momentum():
+    cell = oracle.Cell(rho=0.9, e=1.5, n_c=3, dt=0.005, seed=3)
+    x, v, Ec = oracle.lift(cell)
+    v = v - v.mean(axis=0)
+    r = oracle.run(cell, oracle.Schedule(n_steps=200, n_avg=100), x=x, v=v, Ecold_total=Ec, n_recF=50)
+    for k in range(50):
+        F = r.F[k]
+        # step 0 is the lattice, where every force nearly cancels: the floor
+        # 1e-14 N covers the rounding of the O(10) pair forces themselves
+        assert np.abs(F.sum(axis=0)).max() <= 1e-12 * np.abs(F).sum() + 1e-14 * cell.N
+    assert np.abs(r.v.sum(axis=0)).max() <= 1e-12 * np.abs(r.v).sum()
+
+
+# --- P4: time reversibility ------------------------------------------------------
+
+def test_time_reversibility():
+    cell = oracle.Cell(rho=0.8, e=1.2, n_c=3, dt=0.004, seed=8)
+    x0, v0, Ec = oracle.lift(cell)
+    sch = oracle.Schedule(n_steps=20, n_avg=10, n_blocks=2)
+    a = oracle.run(cell, sch, x=x0, v=v0, Ecold_total=Ec)
+    b = oracle.run(cell, sch, x=a.x, v=-a.v, Ecold_total=Ec)
+    L = oracle.box_length(cell.n_c, cell.rho)
+    d = b.x - x0
+    d -= L * np.rint(d / L)
+    assert np.abs(d).max() <= 1e-9
+    assert np.abs(b.v + v0).max() <= 1e-9
+
+
+# --- P3: velocity-Verlet energy error scales as dt^2 -------------------------------
+
+def test_nve_energy_error_scales_as_dt_squared():
+    cell = oracle.Cell(rho=0.8442, e=1.5, n_c=3, dt=0.004, seed=2)
+    x, v, Ec = oracle.lift(cell)
+    eq = oracle.run(cell, oracle.Schedule(n_steps=400, n_avg=100), x=x, v=v, Ecold_total=Ec)
+    fl = []
+    for dt, n in ((0.004, 200), (0.002, 400)):
+        c = oracle.Cell(rho=cell.rho, e=cell.e, n_c=cell.n_c, dt=dt)
+        r = oracle.run(c, oracle.Schedule(n_steps=n, n_avg=n // 2), x=eq.x, v=eq.v, Ecold_total=Ec)
+        E = r.K + r.U
+        fl.append(np.sqrt(np.mean((E - E.mean()) ** 2)))
+    ratio = fl[0] / fl[1]
+    assert 3.0 < ratio < 5.0, ratio
+
+
+# --- P6: ideal-gas limits -------------------------------------------------------
+
+def test_ideal_gas_without_potential():
+    cell = oracle.Cell(rho=0.5, e=1.3, n_c=3, dt=0.005, seed=4)
+    N = cell.N
+    sch = oracle.Schedule(n_steps=200, n_avg=100, eps=0.0)
+    r = oracle.run(cell, sch)
+    L = oracle.box_length(cell.n_c, cell.rho)
+    V = L ** 3
+    np.testing.assert_allclose(r.P, 2 * r.K / (3 * V), rtol=1e-14)
+    np.testing.assert_allclose(r.P, cell.rho * r.T * (1 - 1 / N), rtol=1e-13)
+    assert r.result.P == pytest.approx(cell.rho * r.result.T * (1 - 1 / N), rel=1e-13)
+    assert r.result.P_se < 1e-12
+
+
+def b2_ljts(T, rc=RC):
+    """Second virial coefficient of the LJTS fluid by 1-D quadrature (SciPy)."""
+    f = lambda r: (math.exp(-float(phi_ts(r, rc)) / T) - 1.0) * r * r
+    pts = [0.8, 1.0, 2 ** (1 / 6), 1.5]
+    val, _ = integrate.quad(f, 1e-6, rc, points=pts, limit=400)
+    return -2 * math.pi * val
+
+
+def test_low_density_virial_limit():
+    rho, T = 0.02, 2.0
+    n_c = 4
+    N = 4 * n_c ** 3
+    e = 1.5 * T * (1 - 1 / N)
+    Z = []
+    for s in range(6):
+        cell = oracle.Cell(rho=rho, e=e, n_c=n_c, dt=0.005, seed=100 + s)
+        sch = oracle.Schedule(n_steps=4000, n_avg=3000, rescale_steps=(300, 700))
+        r = oracle.run(cell, sch)
+        Tm = r.result.T
+        Z.append(r.result.P / (rho * Tm) - (1 - 1 / N))
+        T_used = Tm
+    Z = np.array(Z)
+    se = Z.std(ddof=1) / math.sqrt(len(Z))
+    b2 = b2_ljts(T_used)
+    # third virial term bounded by rho^2 (|B3| < 1 at these T)
+    assert abs(Z.mean() - b2 * rho) <= 3 * se + rho ** 2, (Z.mean(), b2 * rho, se)
+    assert b2 < 0  # attractive regime at T = 2
+
+
+# --- P10: block standard error on an AR(1) series --------------------------------
+
+def test_block_se_matches_ar1_analytic():
+    from scipy.signal import lfilter
+
+    rng = np.random.default_rng(11)
+    phi, n, B, reps = 0.9, 20_000, 10, 400
+    sig = math.sqrt(1 - phi ** 2)
+    se2, means = [], []
+    for _ in range(reps):
+        # stationary unit-variance AR(1): x_t = phi x_{t-1} + sqrt(1 - phi^2) eps_t
+        x0 = rng.normal()
+        x = lfilter([sig], [1.0, -phi], rng.normal(size=n), zi=[phi * x0])[0]
+        m, se = oracle.block_stats(x, B)
+        assert m == pytest.approx(x.mean(), rel=1e-12, abs=1e-15)
+        se2.append(se * se)
+        means.append(m)
+    analytic2 = (1 + phi) / ((1 - phi) * n)
+    # SE^2 of B blocks is an unbiased estimate of the variance of the mean; its
+    # average over the replicas has relative sampling error sqrt(2/(B-1)/reps)
+    tol = 3.5 * math.sqrt(2 / (B - 1) / reps)
+    assert np.mean(se2) == pytest.approx(analytic2, rel=tol)
+    # and the observed spread of the means agrees too
+    assert np.var(means, ddof=1) == pytest.approx(analytic2, rel=3.5 * math.sqrt(2 / reps))

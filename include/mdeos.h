@@ -1,0 +1,246 @@
+/*
+ * mdeos.h -- C ABI of libmdeos, an MI355X (gfx950) engine for the in-line
+ * molecular-dynamics equation of state of arXiv 2508.06012.
+ *
+ * The paper closes the Euler equations with p = f(rho, e) (Sec. II.A,
+ * Eq. EOS) evaluated by an independent MD run at every quadrature point and
+ * every time step (Sec. III). One such evaluation here is a "cell": the
+ * lifting operator maps (rho, e) to a periodic FCC box of N = 4 n_c^3 atoms
+ * with velocities that carry the energy e above the cold lattice (Sec. III,
+ * Eqs. numdens, numAtoms, Tcontribution); the box is advanced with velocity
+ * Verlet (Sec. II.B) in a truncated-shifted Lennard-Jones fluid in reduced
+ * units; the restricting operator returns the time average of one third of
+ * the trace of the kinetic + virial stress (Sec. III, Eq. stress) and the
+ * temperature, with block standard errors.
+ *
+ * Conventions for every call:
+ *   - Host arrays passed in are read during the call only; host arrays passed
+ *     out are written before the call returns. Per-atom host arrays are
+ *     row-major [N][3] doubles. The library owns all device memory.
+ *   - `stream` is a hipStream_t (NULL = the context's own stream). Calls that
+ *     return host results synchronise that stream.
+ *   - Call-level errors are negative mdeos_status values. Per-cell failures
+ *     are MDEOS_CELL_* bits in mdeos_result.status; a batch call returns
+ *     MDEOS_OK even when some cells failed.
+ *   - A context is used by one thread at a time, except the serving calls,
+ *     which are thread-safe.
+ */
+#ifndef MDEOS_H
+#define MDEOS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int mdeos_status;
+
+/* call-level status */
+#define MDEOS_OK 0
+#define MDEOS_INVALID_ARG (-1)
+#define MDEOS_OUT_OF_MEMORY (-2)
+#define MDEOS_DEVICE_ERROR (-3)
+#define MDEOS_NOT_READY (-4)
+#define MDEOS_ADMISSION_FULL (-5)
+#define MDEOS_NO_DEVICE (-6)
+
+/* per-cell status bits (mdeos_result.status) */
+#define MDEOS_CELL_NONFINITE 1          /* K, W or E_pot became NaN/Inf; the cell stopped */
+#define MDEOS_CELL_ENERGY_BELOW_COLD 2  /* a re-pin found N e <= E_pot - E_cold; no rescale */
+#define MDEOS_CELL_DRIFT 4              /* |E(n) - E(n - n_avg)| / N > drift_tol */
+#define MDEOS_CELL_OVERFLOW 8           /* neighbour or ghost capacity exceeded; the cell stopped */
+#define MDEOS_CELL_COLD_RELIFT 16       /* warm start fell back to a cold lift */
+
+#define MDEOS_MAX_RESCALE 8
+#define MDEOS_MAX_BLOCKS 16
+#define MDEOS_MAX_NC 10                 /* N <= 4000 atoms per box */
+
+/* One EOS query (lifting-operator input, Sec. III). */
+typedef struct {
+    double rho;               /* reduced number density rho* > 0 (n = rho in reduced units) */
+    double e;                 /* specific internal energy per atom above the cold lattice, > 0 */
+    int n_c;                  /* FCC cells per edge, 1..MDEOS_MAX_NC; N = 4 n_c^3 */
+    float rc;                 /* LJTS cutoff, 0 < rc < L */
+    double dt;                /* velocity-Verlet time step, > 0 */
+    unsigned long long seed;  /* Philox4x64-10 key word 0 */
+    long long cell_id;        /* Philox4x64-10 key word 1 (and the caller's cell label) */
+} mdeos_cell_spec;
+
+/* Run schedule of one query. */
+typedef struct {
+    int n_steps;                          /* MD steps after the lift, >= 1 */
+    int n_avg;                            /* samples averaged: steps n_steps-n_avg+1 .. n_steps */
+    int n_blocks;                         /* blocks for the standard error, 2..MDEOS_MAX_BLOCKS, divides n_avg */
+    int n_rescale;                        /* 0..MDEOS_MAX_RESCALE energy re-pins (Eq. Tcontribution) */
+    int rescale_steps[MDEOS_MAX_RESCALE]; /* each in [0, n_steps - n_avg]; 0 = right after the lift */
+    int energy_every;                     /* E_pot is computed on steps divisible by this (>= 1) */
+    double drift_tol;                     /* per-atom production drift that sets MDEOS_CELL_DRIFT */
+} mdeos_schedule;
+
+/* Restricted result of one query (restricting operator, Sec. III). */
+typedef struct {
+    double P;          /* <P> = <(2K + W) / (3V)> over the averaging window */
+    double P_se;       /* block standard error of <P> */
+    double P_rms;      /* RMS deviation of the instantaneous P from <P> */
+    double T;          /* <T> = <2K / (3N - 3)> */
+    double T_se;       /* block standard error of <T> */
+    double Epot_mean;  /* <E_pot> / N over energy steps in the window */
+    double Ecold;      /* E_cold / N of the static lattice at rho */
+    double drift;      /* (E(n) - E(n - n_avg)) / N */
+    int n_samples;     /* samples averaged */
+    int status;        /* MDEOS_CELL_* bits */
+} mdeos_result;
+
+typedef struct {
+    int device;                /* HIP device ordinal */
+    size_t hbm_budget;         /* bytes of resident cell state the context may hold; 0 = 64 GiB */
+    float skin;                /* Verlet skin; <= 0 selects 0.3 */
+    int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
+    const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
+} mdeos_config;
+
+typedef struct mdeos_ctx mdeos_ctx;
+typedef long long mdeos_handle;
+
+/* Shape of the device work for one cell, as planned on the host. */
+typedef struct {
+    int N;            /* atoms */
+    float L;          /* box edge */
+    float rl;         /* neighbour-list radius rc + skin */
+    int ext_cap;      /* real + ghost atom capacity */
+    int list_cap;     /* neighbour capacity per atom (multiple of 8) */
+    int ncell;        /* binning cells over the extended box */
+    int lds_bytes;    /* LDS bytes the cell needs */
+    int list_in_lds;  /* 1 if the neighbour list lives in LDS, 0 if in device memory */
+    int multi_image;  /* 1 if rc > L/2 (several periodic images of one atom are in range) */
+} mdeos_plan_info;
+
+/* ---- host-only calls (no device needed) ---------------------------------- */
+
+const char* mdeos_strerror(mdeos_status s);
+/* Message of the last failed call on this thread ("" if none). */
+const char* mdeos_last_error(void);
+const char* mdeos_version(void);
+/* Validates a query and its schedule; MDEOS_OK or MDEOS_INVALID_ARG. */
+mdeos_status mdeos_validate(const mdeos_cell_spec* spec, const mdeos_schedule* sched);
+/* Plans the device work of one query (capacities, LDS bytes, variant). */
+mdeos_status mdeos_plan(const mdeos_cell_spec* spec, float skin, mdeos_plan_info* out);
+/* Device bytes one resident cell of n_c holds (used for HBM admission). */
+size_t mdeos_cell_bytes(int n_c);
+/* Number of visible HIP devices (0 when none or on a host without ROCm devices). */
+int mdeos_device_count(void);
+
+/* ---- context ------------------------------------------------------------ */
+
+mdeos_status mdeos_create(const mdeos_config* cfg, mdeos_ctx** out);
+mdeos_status mdeos_destroy(mdeos_ctx* ctx);
+
+/* ---- lift / advance / restrict (Sec. III) --------------------------------- */
+
+/* Lifting operator: for each spec, builds the FCC lattice (Eq. numdens), its
+ * cold energy, Gaussian velocities at T0 = 2 N e / (3N - 3) with zero net
+ * momentum, scaled so K = N e exactly, and the initial forces. Handles of the
+ * new resident cells are written to out[n]. Cells follow `sched`. */
+mdeos_status mdeos_lift(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched,
+                        mdeos_handle* out, void* stream);
+
+/* Lifts one cell from a given state instead of the lattice draw: xyz and v
+ * ([N][3] doubles; positions are wrapped into [0, L)).
+ * E_cold is always computed from the lattice at spec->rho. */
+mdeos_status mdeos_lift_from_state(mdeos_ctx* ctx, const mdeos_cell_spec* spec, const mdeos_schedule* sched,
+                                   const double* xyz, const double* v, mdeos_handle* out, void* stream);
+
+/* Re-targets resident cells to a new (rho, e) with a warm start: positions
+ * are dilated by L'/L (Eq. numdens at the new density), E_cold is recomputed
+ * at rho', forces are recomputed and the energy is re-pinned to e' at step 0
+ * of `sched` (which must list step 0). If the re-pin finds no kinetic energy
+ * left the cell is lifted cold instead (MDEOS_CELL_COLD_RELIFT). */
+mdeos_status mdeos_warm_start(mdeos_ctx* ctx, int n, const mdeos_handle* h, const double* rho, const double* e,
+                              const mdeos_schedule* sched, void* stream);
+
+/* Advances each cell by up to n_steps velocity-Verlet steps (never past its
+ * schedule's end), in one persistent launch per size bucket. */
+mdeos_status mdeos_advance(mdeos_ctx* ctx, int n, const mdeos_handle* h, int n_steps, void* stream);
+
+/* Restricting operator: writes one result per handle (blocks on the stream).
+ * Cells that have not reached the end of their schedule get MDEOS_NOT_READY
+ * as the call status and their partial averages. */
+mdeos_status mdeos_restrict(mdeos_ctx* ctx, int n, const mdeos_handle* h, mdeos_result* out, void* stream);
+
+/* lift + full schedule + restrict for n cells: one persistent launch per size
+ * bucket, replayed from a cached HIP graph for repeated batch shapes. The
+ * cells are released afterwards. */
+mdeos_status mdeos_eval_batch(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched,
+                              mdeos_result* out, void* stream);
+
+/* The plain path: the same kernels, one cell per launch, cells one after
+ * another on one stream. */
+mdeos_status mdeos_eval_plain(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched,
+                              mdeos_result* out, void* stream);
+
+mdeos_status mdeos_release(mdeos_ctx* ctx, int n, const mdeos_handle* h);
+
+/* Copies a resident cell's state to the host: positions wrapped into [0, L),
+ * velocities, and the number of steps completed. Any pointer may be NULL. */
+mdeos_status mdeos_state_export(mdeos_ctx* ctx, mdeos_handle h, double* xyz, double* v, int* step);
+
+/* ---- parity hooks --------------------------------------------------------- */
+
+/* Forces, potential energy and pair virial sum W = sum_pairs r.f for the
+ * given positions ([N][3], rounded to float, wrapped) of a box described by
+ * spec (N = 4 n_c^3, L from rho), through the same neighbour build and force
+ * kernel as the MD path. F ([N][3]) may be NULL. */
+mdeos_status mdeos_debug_forces(mdeos_ctx* ctx, const mdeos_cell_spec* spec, const double* xyz, double* F,
+                                double* U, double* W);
+
+/* Advances a resident cell by n_steps, one launch per step, with E_pot
+ * computed every step, and records forces (F: (n_steps+1) x N x 3, may be
+ * NULL) and K, U, W (n_steps+1 each, may be NULL) for the starting state and
+ * after each step. */
+mdeos_status mdeos_debug_trajectory(mdeos_ctx* ctx, mdeos_handle h, int n_steps, double* F, double* K, double* U,
+                                    double* W);
+
+/* ---- serving (continuous batching) --------------------------------------- */
+
+typedef struct {
+    mdeos_schedule cold;  /* schedule of a cell's first query (cold lift) */
+    mdeos_schedule warm;  /* schedule of later queries (warm start; must list step 0) */
+    float rc;             /* cutoff of every served cell */
+    double dt;            /* time step of every served cell */
+    unsigned long long seed;
+    int chunk_steps;      /* MD steps per scheduling round, >= 1 */
+    int max_slots;        /* cap on cells advancing at once (0 = as many as HBM allows) */
+} mdeos_serve_config;
+
+typedef struct {
+    long long submitted, completed, cold, warm, relifts, evictions;
+    long long chunks;          /* scheduling rounds launched */
+    long long queued;          /* queries waiting now */
+    long long active;          /* cells advancing now */
+    long long resident;        /* cells with resident state now */
+    size_t resident_bytes;     /* device bytes of resident state */
+    double atom_steps;         /* MD atom-steps executed */
+} mdeos_serve_stats;
+
+/* Starts the scheduler thread. */
+mdeos_status mdeos_serve_start(mdeos_ctx* ctx, const mdeos_serve_config* cfg);
+/* Queues one EOS query for cell `cell_id` at time t_arrival (seconds on the
+ * caller's clock, see mdeos_serve_now). Queries of one cell run in order,
+ * each warm-started from the previous one's final state. */
+mdeos_status mdeos_serve_submit(mdeos_ctx* ctx, long long cell_id, double rho, double e, int n_c, double t_arrival,
+                                long long* ticket);
+/* Returns up to max finished queries: tickets, results and completion times. */
+mdeos_status mdeos_serve_poll(mdeos_ctx* ctx, int max, long long* tickets, mdeos_result* out, double* t_done,
+                              int* n_out);
+/* Seconds on the serving clock (monotonic, zero at mdeos_serve_start). */
+double mdeos_serve_now(mdeos_ctx* ctx);
+mdeos_status mdeos_serve_stats_get(mdeos_ctx* ctx, mdeos_serve_stats* out);
+/* Finishes queued work (drain = 1) or drops it (drain = 0) and joins the thread. */
+mdeos_status mdeos_serve_stop(mdeos_ctx* ctx, int drain);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDEOS_H */

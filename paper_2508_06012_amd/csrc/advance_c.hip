@@ -1,0 +1,9 @@
+// Instantiates the advance kernel for the launch shapes of group C.
+#include "advance_impl.h"
+#include "variants.h"
+
+namespace mdeos {
+#define X(B, A, E, L) MDEOS_DEFINE_VARIANT(B, A, E, L)
+MDEOS_VARIANTS_C(X)
+#undef X
+}  // namespace mdeos

@@ -1,0 +1,1019 @@
+// The persistent advance kernel of libmdeos (included by the per-variant
+// translation units; each instantiates a few launch shapes).
+//
+// One workgroup owns one periodic box at a time ("cell" = one continuum
+// quadrature point's EOS query, Sec. III) and keeps it resident in LDS for a
+// whole chunk of steps:
+//   - lifting operator (Sec. III, Eqs. numdens/numAtoms): FCC lattice at rho,
+//     cold energy of the static lattice, Gaussian velocities (Philox4x64-10 +
+//     Box-Muller) at T0 = 2 N e / N_DOF, zero net momentum, scaled so the
+//     energy above the cold lattice is N e;
+//   - microscopic model (Sec. II.B): velocity Verlet with a Verlet neighbour
+//     list over an LDS-resident extended box (real atoms + periodic ghost
+//     images), LJTS pair forces in FP32 with per-atom FP32 partials promoted to
+//     FP64 for the energy and virial reductions;
+//   - temperature update (Eq. Tcontribution) as an instantaneous energy re-pin
+//     at scheduled steps, in FP64;
+//   - restricting operator (Eq. stress): P = (2K + W) / (3V), T = 2K / N_DOF,
+//     block-averaged in FP64.
+// Every reduction runs in a fixed order over groups of 64 consecutive atoms,
+// and neighbour lists are built in a deterministic order, so a cell's bits do
+// not depend on the launch shape, the batch it runs in, or chunk boundaries.
+#pragma once
+#include "mdeos_dev.h"
+#include "mdeos_host.h"
+
+#define DEVI __device__ __attribute__((always_inline)) inline
+
+namespace mdeos {
+
+namespace {
+
+struct Ctl {
+  int item;
+  int need_rebuild;
+  int stop;
+  int overflow;
+  int n_ext;
+  int wsum[17];
+  float wmax[16];
+  int do_rescale;
+  int pad1;
+  double lam;
+  double scal[4];
+  // accumulators of the cell being advanced (wave 0 owns them)
+  double sumP[kMaxBlocks], sumT[kMaxBlocks];
+  double P_ref, sumdP2, sumU;
+  double E_w0, E_n;
+  double K, U, W;
+  int nU;
+  int status;
+};
+
+DEVI uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// Philox4x64-10 (Salmon et al., SC11): ten rounds, Weyl key schedule.
+DEVI void philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                     uint64_t& o0, uint64_t& o1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t lo0 = M0 * c0, hi0 = mulhi64(M0, c0);
+    uint64_t lo1 = M1 * c2, hi1 = mulhi64(M1, c2);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  o0 = c0; o1 = c1;
+}
+
+// Standard normal of (atom a, component c): Box-Muller on Philox words 0, 1
+// with key (seed, cell_id) and counter (3a + c, 0, 0, 0).
+DEVI double gauss(uint64_t seed, int64_t cell_id, int a, int c) {
+  uint64_t w0, w1;
+  philox4x64_10(seed, (uint64_t)cell_id, (uint64_t)(3 * a + c), 0, 0, 0, w0, w1);
+  const double two_m53 = 1.0 / 9007199254740992.0;
+  double u1 = 1.0 - (double)(w0 >> 11) * two_m53;
+  double u2 = (double)(w1 >> 11) * two_m53;
+  return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+DEVI double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+DEVI float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+DEVI int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+DEVI double wrap1(double x, double L) {
+  // positions move less than L between list builds: one correction suffices
+  if (x >= L) x -= L;
+  else if (x < 0.0) x += L;
+  if (x >= L || x < 0.0) x = 0.0;
+  return x;
+}
+
+template <int BLOCK, int APT, int EXT, bool LLDS>
+struct Box {
+  static constexpr int NW = BLOCK / 64;
+  static constexpr int SENT = EXT - 1;  // padding neighbour index
+
+  const AdvanceParams& p;
+  LdsLayout lay;
+  unsigned char* lds;
+  float* px;  // py = px + EXT, pz = px + 2 EXT
+  uint16_t* list;  // [list_cap/8][n_pad][8]
+  uint16_t *tmp, *sorted;
+  int *cstart, *cfill, *scanbuf;
+  double *ring, *red;
+  Ctl* ctl;
+  int t, lane, wv;
+
+  // cell constants
+  CellRec* c;
+  int N, G, n_pad, list_cap, ncell, nce, R;
+  float L, rl, rl2, rc2, inv_ce;
+  double Lw, dt, hdt;
+  double V, Ndof, u_shift;
+  double Ecold;  // total cold energy (uniform across the workgroup)
+
+  // owned atoms: a = t + k BLOCK
+  // state in FP64 (positions unwrapped since the last list build), forces and
+  // build positions in FP32
+  double x[APT], y[APT], z[APT], vx[APT], vy[APT], vz[APT];
+  float fx[APT], fy[APT], fz[APT], bx[APT], by[APT], bz[APT];
+  float wi[APT];
+  double ui[APT];
+  int gofs[APT], gmask[APT], nblk[APT];
+
+  DEVI Box(const AdvanceParams& pp, unsigned char* l) : p(pp), lds(l) {
+    lay = lds_layout(EXT, p.caps, LLDS);
+    px = (float*)(lds + lay.pos);
+    list = LLDS ? (uint16_t*)(lds + lay.list)
+                : p.gl_list + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
+    tmp = (uint16_t*)(lds + lay.tmp);
+    sorted = (uint16_t*)(lds + lay.sorted);
+    cstart = (int*)(lds + lay.cstart);
+    cfill = (int*)(lds + lay.cfill);
+    scanbuf = (int*)(lds + lay.tmp);
+    ring = (double*)(lds + lay.ring);
+    red = (double*)(lds + lay.red);
+    ctl = (Ctl*)(lds + lay.ctl);
+    t = threadIdx.x;
+    lane = t & 63;
+    wv = t >> 6;
+    n_pad = p.caps.n_pad;
+    list_cap = p.caps.list_cap;
+  }
+
+  DEVI float& PX(int j) { return px[j]; }
+  DEVI float& PY(int j) { return px[EXT + j]; }
+  DEVI float& PZ(int j) { return px[2 * EXT + j]; }
+
+  DEVI void load_cell(int cidx) {
+    c = p.cells + cidx;
+    N = c->N;
+    G = (N + 63) / 64;
+    L = c->L;
+    rl = c->rl;
+    rl2 = rl * rl;
+    rc2 = c->rc * c->rc;
+    dt = c->dt;
+    hdt = 0.5 * dt;
+    Lw = c->Lw;
+    nce = c->nce;
+    R = c->stencil;
+    ncell = nce * nce * nce;
+    inv_ce = (float)nce / (L + 2.0f * rl);
+    V = c->V;
+    Ndof = 3.0 * N - 3.0;
+    double irc2 = 1.0 / ((double)c->rc * (double)c->rc);
+    double irc6 = irc2 * irc2 * irc2;
+    u_shift = 4.0 * (irc6 * irc6 - irc6);
+    Ecold = c->Ecold;
+  }
+
+  // --- block helpers --------------------------------------------------------
+
+  // In-place exclusive scan of arr[0..n) (LDS); returns the total.
+  DEVI int block_scan(int* arr, int n) {
+    const int per = (n + BLOCK - 1) / BLOCK;
+    const int lo = min(t * per, n), hi = min(lo + per, n);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += arr[i];
+    int inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) ctl->wsum[wv] = inc;
+    __syncthreads();
+    if (t == 0) {
+      int acc = 0;
+      for (int w = 0; w < NW; ++w) {
+        int v = ctl->wsum[w];
+        ctl->wsum[w] = acc;
+        acc += v;
+      }
+      ctl->wsum[NW] = acc;
+    }
+    __syncthreads();
+    int run = ctl->wsum[wv] + inc - s;
+    for (int i = lo; i < hi; ++i) {
+      int v = arr[i];
+      arr[i] = run;
+      run += v;
+    }
+    int total = ctl->wsum[NW];
+    __syncthreads();
+    return total;
+  }
+
+  // Per-group (64 consecutive atoms) FP64 sums of three per-atom values into
+  // dst[g][0..2]; each wave writes its own groups.
+  DEVI void group_sums(const double (&a)[APT], const double (&b)[APT], const double (&cc)[APT], double* dst) {
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      double sa = wave_sum(a[k]), sb = wave_sum(b[k]), sc = wave_sum(cc[k]);
+      int g = k * NW + wv;
+      if (lane == 0 && g < p.caps.gmax) {
+        dst[3 * g + 0] = sa;
+        dst[3 * g + 1] = sb;
+        dst[3 * g + 2] = sc;
+      }
+    }
+  }
+
+  // Block-wide FP64 sums of three per-atom values, summed over groups in
+  // index order; the result is visible to every thread.
+  DEVI void reduce_now(const double (&a)[APT], const double (&b)[APT], const double (&cc)[APT], double& A,
+                             double& B, double& C) {
+    group_sums(a, b, cc, red);
+    __syncthreads();
+    if (t == 0) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int g = 0; g < G; ++g) {
+        s0 += red[3 * g + 0];
+        s1 += red[3 * g + 1];
+        s2 += red[3 * g + 2];
+      }
+      ctl->scal[0] = s0;
+      ctl->scal[1] = s1;
+      ctl->scal[2] = s2;
+    }
+    __syncthreads();
+    A = ctl->scal[0];
+    B = ctl->scal[1];
+    C = ctl->scal[2];
+    __syncthreads();
+  }
+
+  DEVI bool valid(int k) const { return t + k * BLOCK < N; }
+
+  // --- neighbour structures -------------------------------------------------
+
+  DEVI int ghost_mask(float xx, float yy, float zz) const {
+    int m = 0;
+    m |= (xx < rl) ? 1 : 0;
+    m |= (xx >= L - rl) ? 2 : 0;
+    m |= (yy < rl) ? 4 : 0;
+    m |= (yy >= L - rl) ? 8 : 0;
+    m |= (zz < rl) ? 16 : 0;
+    m |= (zz >= L - rl) ? 32 : 0;
+    return m;
+  }
+  DEVI static int n_images(int m) {
+    int nx = 1 + (m & 1) + ((m >> 1) & 1);
+    int ny = 1 + ((m >> 2) & 1) + ((m >> 3) & 1);
+    int nz = 1 + ((m >> 4) & 1) + ((m >> 5) & 1);
+    return nx * ny * nz - 1;
+  }
+
+  // Writes the periodic images of one atom at (xx, yy, zz) starting at ghost
+  // slot g, in the fixed order sx, sy, sz in {-1, 0, 1} (lexicographic). An
+  // image with shift +1 exists when the coordinate is below rl, -1 when it is
+  // at least L - rl: exactly the images that fall in [-rl, L + rl).
+  DEVI void write_images(double xx, double yy, double zz, int m, int g) {
+#pragma unroll 1
+    for (int sx = -1; sx <= 1; ++sx) {
+      if ((sx == 1 && !(m & 1)) || (sx == -1 && !(m & 2))) continue;
+#pragma unroll 1
+      for (int sy = -1; sy <= 1; ++sy) {
+        if ((sy == 1 && !(m & 4)) || (sy == -1 && !(m & 8))) continue;
+#pragma unroll 1
+        for (int sz = -1; sz <= 1; ++sz) {
+          if ((sz == 1 && !(m & 16)) || (sz == -1 && !(m & 32))) continue;
+          if (sx == 0 && sy == 0 && sz == 0) continue;
+          PX(g) = (float)(xx + sx * Lw);
+          PY(g) = (float)(yy + sy * Lw);
+          PZ(g) = (float)(zz + sz * Lw);
+          ++g;
+        }
+      }
+    }
+  }
+
+  DEVI int cell_coord(float v) const {
+    int q = (int)floorf((v + rl) * inv_ce);
+    return min(max(q, 0), nce - 1);
+  }
+  DEVI int cell_of(int e) { return (cell_coord(PZ(e)) * nce + cell_coord(PY(e))) * nce + cell_coord(PX(e)); }
+
+  // Builds ghosts, the binning and every atom's neighbour list from the
+  // build positions (bx, by, bz). Returns false on a capacity overflow.
+  DEVI bool build_lists() {
+    // real atoms at their build positions; ghost counts
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      gmask[k] = 0;
+      if (a < N) {
+        PX(a) = bx[k];
+        PY(a) = by[k];
+        PZ(a) = bz[k];
+        gmask[k] = ghost_mask(bx[k], by[k], bz[k]);
+        scanbuf[a] = n_images(gmask[k]);
+      }
+    }
+    __syncthreads();
+    int n_ghost = block_scan(scanbuf, N);
+    int n_ext = N + n_ghost;
+    if (n_ext > SENT || ncell > p.caps.ncell_cap) {
+      if (t == 0) atomicMax(&c->max_ext, n_ext);
+      return false;
+    }
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      if (a < N) {
+        gofs[k] = N + scanbuf[a];
+        write_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k], gofs[k]);
+      }
+    }
+    for (int q = t; q < ncell; q += BLOCK) {
+      cstart[q] = 0;
+      cfill[q] = 0;
+    }
+    if (t == 0) cstart[ncell] = 0;
+    __syncthreads();
+    // bin every extended atom
+    for (int e = t; e < n_ext; e += BLOCK) atomicAdd(&cstart[cell_of(e)], 1);
+    __syncthreads();
+    block_scan(cstart, ncell + 1);
+    for (int e = t; e < n_ext; e += BLOCK) {
+      int cq = cell_of(e);
+      int s = atomicAdd(&cfill[cq], 1);
+      tmp[cstart[cq] + s] = (uint16_t)e;
+    }
+    __syncthreads();
+    // stable order inside each cell: rank by extended index
+    for (int e = t; e < n_ext; e += BLOCK) {
+      int cq = cell_of(e);
+      int lo = cstart[cq], hi = cstart[cq + 1];
+      int r = 0;
+      for (int q = lo; q < hi; ++q) r += (tmp[q] < e) ? 1 : 0;
+      sorted[lo + r] = (uint16_t)e;
+    }
+    __syncthreads();
+    // neighbour lists: rows of the (2R+1)^3 stencil in fixed order
+    int over = 0;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      int cnt = 0;
+      if (a < N) {
+        const float xi = bx[k], yi = by[k], zi = bz[k];
+        const int cx = cell_coord(xi), cy = cell_coord(yi), cz = cell_coord(zi);
+        const int x0 = max(cx - R, 0), x1 = min(cx + R, nce - 1);
+        for (int dz = -R; dz <= R; ++dz) {
+          const int zz = cz + dz;
+          if (zz < 0 || zz >= nce) continue;
+          for (int dy = -R; dy <= R; ++dy) {
+            const int yy = cy + dy;
+            if (yy < 0 || yy >= nce) continue;
+            const int row = (zz * nce + yy) * nce;
+            const int lo = cstart[row + x0], hi = cstart[row + x1 + 1];
+            for (int q = lo; q < hi; ++q) {
+              const int e = sorted[q];
+              const float ddx = xi - PX(e), ddy = yi - PY(e), ddz = zi - PZ(e);
+              const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+              if (r2 < rl2 && e != a) {
+                if (cnt < list_cap) list[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)(4 * e);
+                ++cnt;
+              }
+            }
+          }
+        }
+      }
+      over |= (cnt > list_cap) ? 1 : 0;
+      int cm = wave_max_i(cnt);
+      if (lane == 0 && cm > 0) atomicMax(&c->max_list, cm);
+      cm = min(cm, list_cap);
+      int nb = __builtin_amdgcn_readfirstlane((cm + 7) >> 3);
+      nblk[k] = nb;
+      // pad every lane of the wave (also atoms past N) to nb blocks
+      if (a < n_pad) {
+        int from = (a < N) ? min(cnt, list_cap) : 0;
+        for (int q = from; q < 8 * nb; ++q) list[(((q >> 3) * n_pad + a) << 3) + (q & 7)] = (uint16_t)(4 * SENT);
+      }
+    }
+    if (over) ctl->overflow = 1;
+    __syncthreads();
+    bool ok = ctl->overflow == 0;
+    if (t == 0) {
+      atomicMax(&c->max_ext, n_ext);
+      c->n_builds += 1;
+    }
+    ctl->n_ext = n_ext;
+    return ok;
+  }
+
+  // Current positions of real atoms and their ghost images into LDS.
+  DEVI void refresh_positions() {
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      if (a < N) {
+        PX(a) = (float)x[k];
+        PY(a) = (float)y[k];
+        PZ(a) = (float)z[k];
+        if (gmask[k]) write_images(x[k], y[k], z[k], gmask[k], gofs[k]);
+      }
+    }
+  }
+
+  // Wrap the current positions into [0, L) and rebuild the lists from them.
+  DEVI bool rebuild() {
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      if (valid(k)) {
+        x[k] = wrap1(x[k], Lw);
+        y[k] = wrap1(y[k], Lw);
+        z[k] = wrap1(z[k], Lw);
+      }
+      bx[k] = (float)x[k];
+      by[k] = (float)y[k];
+      bz[k] = (float)z[k];
+    }
+    return build_lists();
+  }
+
+  // --- pair forces (LJTS, FP32) -------------------------------------------------
+  // For every listed neighbour j of i with r^2 < rc^2:
+  //   f_ij = 24 r^-2 r^-6 (2 r^-6 - 1) d, pair virial r.f = 24 r^-6 (2 r^-6 - 1),
+  //   energy 4 r^-6 (r^-6 - 1) - 4 (rc^-12 - rc^-6).
+  // Neighbours between rc and rl and the padding entries add exact zeros.
+  template <bool ENERGY>
+  DEVI void forces() {
+    const uint4* lb = reinterpret_cast<const uint4*>(list);
+    const char* pb = reinterpret_cast<const char*>(px);
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      const int a = t + k * BLOCK;
+      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
+      float ax = 0.f, ay = 0.f, az = 0.f, w = 0.f;
+      double u = 0.0;  // pair energies are summed in FP64 (energy steps only)
+      int cin = 0;
+      const int nb = nblk[k];
+      if (a < n_pad) {
+        for (int b = 0; b < nb; ++b) {
+          const uint4 ent = lb[b * n_pad + a];
+          const uint32_t wd[4] = {ent.x, ent.y, ent.z, ent.w};
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const uint32_t off = (m & 1) ? (wd[m >> 1] >> 16) : (wd[m >> 1] & 0xffffu);
+            const float* q = reinterpret_cast<const float*>(pb + off);
+            const float dx = xi - q[0], dy = yi - q[EXT], dz = zi - q[2 * EXT];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const bool in = r2 < rc2;
+            const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
+            const float ir6 = ir2 * ir2 * ir2;
+            const float vir = fmaf(48.0f, ir6, -24.0f) * ir6;
+            const float ff = vir * ir2;
+            w += vir;
+            ax = fmaf(ff, dx, ax);
+            ay = fmaf(ff, dy, ay);
+            az = fmaf(ff, dz, az);
+            if (ENERGY) {
+              u += (double)fmaf(ir6, ir6, -ir6);
+              cin += in ? 1 : 0;
+            }
+          }
+        }
+      }
+      fx[k] = ax;
+      fy[k] = ay;
+      fz[k] = az;
+      wi[k] = w;
+      ui[k] = ENERGY ? 4.0 * u - (double)cin * u_shift : 0.0;
+    }
+  }
+
+  // --- per-step bookkeeping (FP64) --------------------------------------------------
+
+  DEVI bool is_rescale(int k) const {
+    for (int r = 0; r < c->n_rescale; ++r)
+      if (c->rescale_steps[r] == k) return true;
+    return false;
+  }
+  DEVI bool is_energy_step(int k) const {
+    const int n = c->n_steps, w0 = n - c->n_avg;
+    return c->debug_energy || (k % c->energy_every == 0) || k == n || k == w0 || is_rescale(k);
+  }
+
+  // Observables of step k from the block sums (wave 0 only; all lanes compute
+  // the same values, lane 0 writes). Eq. stress: P = (2K + W) / (3V).
+  DEVI void observe(int k, double K, double W, double U, bool energy) {
+    const int n = c->n_steps, w0 = n - c->n_avg;
+    const double P = (2.0 * K + W) / (3.0 * V);
+    const double T = 2.0 * K / Ndof;
+    bool bad = !isfinite(K) || !isfinite(W) || (energy && !isfinite(U));
+    if (lane == 0) {
+      if (bad) {
+        ctl->status |= ST_NONFINITE;
+        ctl->stop = 1;
+      }
+      ctl->K = K;
+      ctl->W = W;
+      if (energy) ctl->U = U;
+      if (k > w0) {
+        const int idx = k - w0 - 1;
+        const int bl = c->n_avg / c->n_blocks;
+        const int b = idx / bl;
+        ctl->sumP[b] += P;
+        ctl->sumT[b] += T;
+        if (idx == 0) ctl->P_ref = P;
+        const double dp = P - ctl->P_ref;
+        ctl->sumdP2 += dp * dp;
+        if (energy && (k % c->energy_every == 0 || k == n)) {
+          ctl->sumU += U;
+          ctl->nU += 1;
+        }
+      }
+      if (k == w0) ctl->E_w0 = K + U;
+      if (k == n) ctl->E_n = K + U;
+    }
+  }
+
+  // Steps k_first..k_last have their group sums in ring slots (k % ring).
+  DEVI void flush(int k_first, int k_last) {
+    if (wv != 0 || k_last < k_first) return;
+    const int R = p.caps.ring;
+    const int cnt = k_last - k_first + 1;
+    double Ks = 0.0, Ws = 0.0, Us = 0.0;
+    if (lane < cnt) {
+      const double* r = ring + (size_t)((k_first + lane) % R) * 3 * p.caps.gmax;
+      for (int g = 0; g < G; ++g) {
+        Ks += r[3 * g + 0];
+        Ws += r[3 * g + 1];
+        Us += r[3 * g + 2];
+      }
+    }
+    for (int s = 0; s < cnt; ++s) {
+      const double K = __shfl(Ks, s, 64), W = __shfl(Ws, s, 64), U = __shfl(Us, s, 64);
+      const int k = k_first + s;
+      observe(k, K, W, U, is_energy_step(k));
+    }
+  }
+
+  // --- load / store ------------------------------------------------------------------
+
+  DEVI void load_state() {
+    const int off = c->atom_off;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      if (a < N) {
+        x[k] = p.a.x[off + a]; y[k] = p.a.y[off + a]; z[k] = p.a.z[off + a];
+        vx[k] = p.a.vx[off + a]; vy[k] = p.a.vy[off + a]; vz[k] = p.a.vz[off + a];
+        fx[k] = p.a.fx[off + a]; fy[k] = p.a.fy[off + a]; fz[k] = p.a.fz[off + a];
+        bx[k] = p.a.bx[off + a]; by[k] = p.a.by[off + a]; bz[k] = p.a.bz[off + a];
+      } else {
+        x[k] = y[k] = z[k] = vx[k] = vy[k] = vz[k] = 0.0;
+        fx[k] = fy[k] = fz[k] = bx[k] = by[k] = bz[k] = 0.f;
+      }
+    }
+  }
+  DEVI void store_state() {
+    const int off = c->atom_off;
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      if (a < N) {
+        p.a.x[off + a] = x[k]; p.a.y[off + a] = y[k]; p.a.z[off + a] = z[k];
+        p.a.vx[off + a] = vx[k]; p.a.vy[off + a] = vy[k]; p.a.vz[off + a] = vz[k];
+        p.a.fx[off + a] = fx[k]; p.a.fy[off + a] = fy[k]; p.a.fz[off + a] = fz[k];
+        p.a.bx[off + a] = bx[k]; p.a.by[off + a] = by[k]; p.a.bz[off + a] = bz[k];
+      }
+    }
+  }
+  DEVI void load_acc() {
+    if (t == 0) {
+      for (int b = 0; b < kMaxBlocks; ++b) {
+        ctl->sumP[b] = c->sumP[b];
+        ctl->sumT[b] = c->sumT[b];
+      }
+      ctl->P_ref = c->P_ref; ctl->sumdP2 = c->sumdP2; ctl->sumU = c->sumU; ctl->nU = c->nU;
+      ctl->E_w0 = c->E_w0; ctl->E_n = c->E_n; ctl->K = c->K; ctl->U = c->U; ctl->W = c->W;
+      ctl->status = c->status;
+      ctl->stop = 0;
+      ctl->overflow = 0;
+    }
+  }
+  DEVI void clear_acc() {
+    if (t == 0) {
+      for (int b = 0; b < kMaxBlocks; ++b) ctl->sumP[b] = ctl->sumT[b] = 0.0;
+      ctl->P_ref = ctl->sumdP2 = ctl->sumU = 0.0;
+      ctl->nU = 0;
+      ctl->E_w0 = ctl->E_n = ctl->K = ctl->U = ctl->W = 0.0;
+      ctl->status = 0;
+      ctl->stop = 0;
+      ctl->overflow = 0;
+    }
+  }
+  DEVI void store_acc(int step, int phase) {
+    if (t == 0) {
+      for (int b = 0; b < kMaxBlocks; ++b) {
+        c->sumP[b] = ctl->sumP[b];
+        c->sumT[b] = ctl->sumT[b];
+      }
+      c->P_ref = ctl->P_ref; c->sumdP2 = ctl->sumdP2; c->sumU = ctl->sumU; c->nU = ctl->nU;
+      c->E_w0 = ctl->E_w0; c->E_n = ctl->E_n; c->K = ctl->K; c->U = ctl->U; c->W = ctl->W;
+      c->status = ctl->status;
+      c->step = step;
+      c->phase = phase;
+    }
+  }
+
+  // --- lift pieces ----------------------------------------------------------------------
+
+  // FCC lattice at the cell's density, l = (4 / rho)^(1/3) (Eq. numdens with
+  // alpha = 4): atom a = 4((ix n_c + iy) n_c + iz) + b at l((ix,iy,iz) + basis_b + 1/4).
+  DEVI void lattice_positions(double rho) {
+    const int nc = c->n_c;
+    const double l = cbrt(4.0 / rho);
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      if (a < N) {
+        int b = a & 3, cell = a >> 2;
+        int iz = cell % nc, iy = (cell / nc) % nc, ix = cell / (nc * nc);
+        double ox = (b == 2 || b == 3) ? 0.5 : 0.0;
+        double oy = (b == 1 || b == 3) ? 0.5 : 0.0;
+        double oz = (b == 1 || b == 2) ? 0.5 : 0.0;
+        // rounded to float like the stored lattice of the oracle
+        x[k] = (double)(float)(l * (ix + ox + 0.25));
+        y[k] = (double)(float)(l * (iy + oy + 0.25));
+        z[k] = (double)(float)(l * (iz + oz + 0.25));
+      } else {
+        x[k] = y[k] = z[k] = 0.0;
+      }
+    }
+  }
+
+  // Forces, E_pot and W at the current positions with fresh lists.
+  // Returns false on overflow.
+  DEVI bool full_force_pass(double& U, double& W) {
+    if (!rebuild()) return false;
+    refresh_positions();
+    __syncthreads();
+    forces<true>();
+    double ua[APT], wa[APT], za[APT];
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      bool v = valid(k);
+      ua[k] = v ? ui[k] : 0.0;
+      wa[k] = v ? (double)wi[k] : 0.0;
+      za[k] = 0.0;
+    }
+    double zz;
+    reduce_now(ua, wa, za, U, W, zz);
+    U *= 0.5;  // full lists count every pair twice
+    W *= 0.5;
+    return true;
+  }
+
+  DEVI double kinetic_now() {
+    double ka[APT], za[APT];
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      ka[k] = valid(k) ? 0.5 * (vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]) : 0.0;
+      za[k] = 0.0;
+    }
+    double K, z1, z2;
+    reduce_now(ka, za, za, K, z1, z2);
+    return K;
+  }
+
+  // Cold energy: E_pot of the static lattice at the cell's density.
+  DEVI bool cold_energy(double& Ec) {
+    lattice_positions(c->rho);
+    double W;
+    return full_force_pass(Ec, W);
+  }
+
+  // Gaussian velocities at T0 = 2 N e / N_DOF, centre of mass removed, scaled
+  // so K = N e exactly (FP64), then rounded to float.
+  DEVI void draw_velocities() {
+    const double T0 = 2.0 * N * c->e / Ndof;
+    const double sT = sqrt(T0);
+    double v0[APT], v1[APT], v2[APT];
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      int a = t + k * BLOCK;
+      if (a < N) {
+        v0[k] = gauss(c->seed, c->cell_id, a, 0) * sT;
+        v1[k] = gauss(c->seed, c->cell_id, a, 1) * sT;
+        v2[k] = gauss(c->seed, c->cell_id, a, 2) * sT;
+      } else {
+        v0[k] = v1[k] = v2[k] = 0.0;
+      }
+    }
+    double m0, m1, m2;
+    reduce_now(v0, v1, v2, m0, m1, m2);
+    m0 /= N; m1 /= N; m2 /= N;
+    double ke[APT], za[APT];
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      if (valid(k)) {
+        v0[k] -= m0; v1[k] -= m1; v2[k] -= m2;
+        ke[k] = 0.5 * (v0[k] * v0[k] + v1[k] * v1[k] + v2[k] * v2[k]);
+      } else {
+        ke[k] = 0.0;
+      }
+      za[k] = 0.0;
+    }
+    double K, z1, z2;
+    reduce_now(ke, za, za, K, z1, z2);
+    const double lam = sqrt(N * c->e / K);
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      // rounded to float: the lifted state is float-representable (as in the oracle)
+      vx[k] = valid(k) ? (double)(float)(v0[k] * lam) : 0.0;
+      vy[k] = valid(k) ? (double)(float)(v1[k] * lam) : 0.0;
+      vz[k] = valid(k) ? (double)(float)(v2[k] * lam) : 0.0;
+    }
+  }
+
+  // Step-0 record after a lift: observables (and the re-pin when 0 is
+  // scheduled). U0, W0 are the energy and virial of the current positions.
+  DEVI void record_step0(double U0, double W0) {
+    double K = kinetic_now();
+    if (is_rescale(0)) {
+      const double Kt = N * c->e - (U0 - Ecold);
+      if (Kt <= 0.0) {
+        if (t == 0) ctl->status |= ST_BELOW_COLD;
+      } else {
+        const double lam = sqrt(Kt / K);
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+          vx[k] *= lam; vy[k] *= lam; vz[k] *= lam;
+        }
+        K = kinetic_now();
+      }
+    }
+    if (wv == 0) observe(0, K, W0, U0, true);
+    __syncthreads();
+  }
+
+  // --- the cell -----------------------------------------------------------------------
+
+  DEVI void run(int cidx) {
+    load_cell(cidx);
+    const int phase = c->phase;
+    if (phase == PH_DONE) return;
+    if (phase == PH_RUN) {
+      const int step = c->step;
+      load_acc();
+      load_state();
+      __syncthreads();
+      if (!build_lists()) {
+        fail_overflow(step);
+        return;
+      }
+      refresh_positions();
+      advance_steps(step);
+      return;
+    }
+    clear_acc();
+    __syncthreads();
+    double Ec = 0.0, U0 = 0.0, W0 = 0.0;
+    if (phase == PH_FORCES) {
+      load_state();
+      if (!full_force_pass(U0, W0)) {
+        fail_overflow(0);
+        return;
+      }
+#pragma unroll
+      for (int k = 0; k < APT; ++k) vx[k] = vy[k] = vz[k] = 0.0;
+      store_state();
+      if (t == 0) {
+        c->U = U0;
+        c->W = W0;
+        c->K = 0.0;
+        c->phase = PH_DONE;
+        c->status = 0;
+      }
+      return;
+    }
+    // lifting operator: E_cold of the static lattice at rho
+    lattice_positions(c->rho);
+    if (!full_force_pass(Ec, W0)) {
+      fail_overflow(0);
+      return;
+    }
+    if (t == 0) c->Ecold = Ec;
+    Ecold = Ec;
+    U0 = Ec;
+    bool cold = phase == PH_COLD;
+    if (!cold) {
+      load_state();
+      if (phase == PH_WARM) {
+        // dilate the resident configuration to the new box: x <- x L'/L
+        const double Lold = c->Lw / c->warm_scale;
+        const double s = c->warm_scale;
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+          if (valid(k)) {
+            x[k] = wrap1(wrap1(x[k], Lold) * s, Lw);
+            y[k] = wrap1(wrap1(y[k], Lold) * s, Lw);
+            z[k] = wrap1(wrap1(z[k], Lold) * s, Lw);
+          }
+        }
+      }
+      __syncthreads();
+      if (!full_force_pass(U0, W0)) {
+        fail_overflow(0);
+        return;
+      }
+      if (phase == PH_WARM && !(N * c->e - (U0 - Ec) > 0.0)) {
+        // no kinetic energy left above the new cold lattice: lift cold instead
+        cold = true;
+        if (t == 0) ctl->status |= ST_COLD_RELIFT;
+        lattice_positions(c->rho);
+        if (!full_force_pass(U0, W0)) {
+          fail_overflow(0);
+          return;
+        }
+      }
+    }
+    if (cold) draw_velocities();
+    record_step0(U0, W0);
+    advance_steps(0);
+  }
+
+  DEVI void fail_overflow(int step) {
+    if (t == 0) {
+      c->status |= ST_OVERFLOW;
+      c->phase = PH_DONE;
+      c->step = step;
+    }
+  }
+
+  DEVI void advance_steps(int step) {
+    const int n = c->n_steps;
+    int target = n;
+    if (p.step_budget > 0) target = min(n, step + p.step_budget);
+    else if (p.step_budget < 0) target = step;
+    const int RING = p.caps.ring;
+    const float thr = 0.25f * (rl - sqrtf(rc2)) * (rl - sqrtf(rc2));  // (skin / 2)^2
+    int pending = step + 1;  // first step not yet flushed
+    __syncthreads();
+    bool stopped = ctl->stop != 0;
+    while (step < target && !stopped) {
+      const int k = step + 1;
+      // kick + drift, own ghosts, displacement since the build
+      float dm = 0.f;
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        if (valid(q)) {
+          vx[q] = fma(hdt, (double)fx[q], vx[q]);
+          vy[q] = fma(hdt, (double)fy[q], vy[q]);
+          vz[q] = fma(hdt, (double)fz[q], vz[q]);
+          x[q] = fma(dt, vx[q], x[q]);
+          y[q] = fma(dt, vy[q], y[q]);
+          z[q] = fma(dt, vz[q], z[q]);
+          const float ex = (float)x[q] - bx[q], ey = (float)y[q] - by[q], ez = (float)z[q] - bz[q];
+          dm = fmaxf(dm, ex * ex + ey * ey + ez * ez);
+        }
+      }
+      dm = wave_max(dm);
+      if (lane == 0) ctl->wmax[wv] = dm;
+      __syncthreads();
+      float gm = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) gm = fmaxf(gm, ctl->wmax[w]);
+      if (gm > thr) {
+        __syncthreads();
+        if (!rebuild()) {
+          flush(pending, step);
+          __syncthreads();
+          store_acc(step, PH_DONE);
+          if (t == 0) c->status |= ST_OVERFLOW;
+          return;
+        }
+      }
+      refresh_positions();
+      __syncthreads();
+      const bool energy = is_energy_step(k);
+      if (energy) forces<true>();
+      else forces<false>();
+      double ka[APT], wa[APT], ua[APT];
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        vx[q] = fma(hdt, (double)fx[q], vx[q]);
+        vy[q] = fma(hdt, (double)fy[q], vy[q]);
+        vz[q] = fma(hdt, (double)fz[q], vz[q]);
+        const bool v = valid(q);
+        ka[q] = v ? 0.5 * (vx[q] * vx[q] + vy[q] * vy[q] + vz[q] * vz[q]) : 0.0;
+        wa[q] = v ? 0.5 * (double)wi[q] : 0.0;
+        ua[q] = (v && energy) ? 0.5 * ui[q] : 0.0;
+      }
+      group_sums(ka, wa, ua, ring + (size_t)(k % RING) * 3 * p.caps.gmax);
+      step = k;
+      __syncthreads();
+      if (is_rescale(k)) {
+        // energy re-pin (Eq. Tcontribution): K <- N e - (E_pot - E_cold)
+        flush(pending, k - 1);
+        if (t == 0) {
+          const double* r = ring + (size_t)(k % RING) * 3 * p.caps.gmax;
+          double K = 0.0, W = 0.0, U = 0.0;
+          for (int g = 0; g < G; ++g) {
+            K += r[3 * g + 0];
+            W += r[3 * g + 1];
+            U += r[3 * g + 2];
+          }
+          const double Kt = N * c->e - (U - Ecold);
+          ctl->do_rescale = (Kt > 0.0 && isfinite(Kt)) ? 1 : 0;
+          ctl->lam = (Kt > 0.0) ? sqrt(Kt / K) : 1.0;
+          if (!(Kt > 0.0)) ctl->status |= ST_BELOW_COLD;
+          ctl->scal[3] = W;
+          ctl->scal[2] = U;
+        }
+        __syncthreads();
+        const double W = ctl->scal[3], U = ctl->scal[2];
+        double K;
+        if (ctl->do_rescale) {
+          const double lam = ctl->lam;
+#pragma unroll
+          for (int q = 0; q < APT; ++q) {
+            vx[q] *= lam; vy[q] *= lam; vz[q] *= lam;
+          }
+        }
+        K = kinetic_now();
+        if (wv == 0) observe(k, K, W, U, true);
+        pending = k + 1;
+        __syncthreads();
+      } else if (k - pending + 1 >= RING || k == target) {
+        flush(pending, k);
+        pending = k + 1;
+        __syncthreads();
+      }
+      stopped = ctl->stop != 0;
+    }
+    if (pending <= step) {
+      flush(pending, step);
+      __syncthreads();
+    }
+    store_state();
+    const bool done = (step >= n) || stopped;
+    store_acc(step, done ? PH_DONE : PH_RUN);
+  }
+};
+
+template <int BLOCK, int APT, int EXT, bool LLDS>
+__global__ void __launch_bounds__(BLOCK) k_advance(AdvanceParams p) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  Box<BLOCK, APT, EXT, LLDS> box(p, lds);
+  if (threadIdx.x == 0) {
+    box.PX(EXT - 1) = kSentinelPos;
+    box.PY(EXT - 1) = kSentinelPos;
+    box.PZ(EXT - 1) = kSentinelPos;
+  }
+  const int n_work = p.meta[0];
+  const int* work = p.work_base + p.meta[1];
+  for (;;) {
+    if (threadIdx.x == 0) box.ctl->item = atomicAdd(p.counter, 1);
+    __syncthreads();
+    const int item = box.ctl->item;
+    __syncthreads();
+    if (item >= n_work) break;
+    box.run(work[item]);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Host-side wrappers of one launch shape, defined in the variant translation units.
+#define MDEOS_DEFINE_VARIANT(B, A, E, L)                                                                   \
+  namespace variants {                                                                                    \
+  hipError_t launch_##B##_##A##_##E##_##L(const AdvanceParams& p, int grid, int lds, hipStream_t s) {      \
+    hipLaunchKernelGGL((k_advance<B, A, E, L != 0>), dim3(grid), dim3(B), lds, s, p);                      \
+    return hipGetLastError();                                                                              \
+  }                                                                                                       \
+  hipError_t attr_##B##_##A##_##E##_##L() {                                                               \
+    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0>,                                   \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                       \
+  }                                                                                                       \
+  int occ_##B##_##A##_##E##_##L(int lds) {                                                                \
+    int n = 0;                                                                                            \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0>, B, lds) != \
+        hipSuccess)                                                                                       \
+      n = 1;                                                                                              \
+    return n;                                                                                             \
+  }                                                                                                       \
+  }
+
+}  // namespace mdeos

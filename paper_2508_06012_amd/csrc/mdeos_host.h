@@ -1,0 +1,201 @@
+// Host-side internals of libmdeos: the context, the device arena allocator,
+// per-cell plans, launch buckets and the serving state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mdeos.h"
+#include "mdeos_dev.h"
+
+namespace mdeos {
+
+constexpr int kLdsMax = 160 * 1024;
+constexpr int kAux = 4;
+constexpr int kMaxBuckets = 64;
+
+double box_length(int n_c, double rho);
+int ring_for(int gmax);
+
+struct CellPlan {
+  int N = 0;
+  double Lw = 0.0;
+  float L = 0.f, rl = 0.f;
+  int stencil = 1, nce = 0, ncell = 0;
+  int ext_need = 0, ext = 0;
+  int list_cap = 0;
+  int list_in_lds = 0;
+  int lds_bytes = 0;
+  int multi_image = 0;
+};
+
+mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out);
+
+// First-fit allocator of integer ranges with coalescing.
+class RangeAlloc {
+ public:
+  int alloc(int n);
+  void release(int off, int n);
+  void grow(int old_cap, int new_cap);
+  bool has_room(int n) const {
+    for (auto& kv : free_)
+      if (kv.second >= n) return true;
+    return false;
+  }
+  long long used() const { return used_; }
+
+ private:
+  void release_raw(int off, int n);
+  std::map<int, int> free_;
+  long long used_ = 0;
+};
+
+struct Bucket {
+  Variant v{};
+  Caps caps{0, 0, 0, 0, 0};
+  int lds = 0;
+  int grid = 1;
+  int work_off = 0;
+  size_t gl_off = 0;
+  std::vector<int> cells;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+};
+
+// Kernel helpers implemented in kernels.hip.
+hipError_t init_kernel_attributes();
+int occupancy(const Variant& v, int lds_bytes);
+
+struct ServeQuery {
+  long long ticket;
+  long long cell_id;
+  double rho, e;
+  int n_c;
+  double t_arrival;
+};
+
+struct ServeDone {
+  long long ticket;
+  mdeos_result res;
+  double t_done;
+};
+
+struct ServeCell {
+  int slot = -1;           // resident slot, -1 if none
+  bool busy = false;       // a query of this cell is advancing
+  long long last_use = 0;  // scheduling round of the last query
+  std::deque<ServeQuery> pending;
+};
+
+struct Ctx {
+  int device = 0;
+  int n_cu = 256;
+  float skin = 0.3f;
+  size_t hbm_budget = 0;
+  int autotune = 0;
+  std::string tune_cache;
+  std::recursive_mutex mu;
+
+  hipStream_t own_stream = nullptr;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kAux] = {}, ev_t0 = nullptr, ev_t1 = nullptr;
+
+  // atom arena: 6 FP64 arrays (x, v) and 6 FP32 arrays (F, build positions)
+  std::vector<void*> arena_ptrs;
+  AtomArena arena{};
+  int atom_cap = 0;
+  RangeAlloc atoms;
+
+  // cells
+  CellRec* d_cells = nullptr;
+  int cell_cap = 0;
+  RangeAlloc slots;
+  std::vector<CellRec> h_cells;
+  std::vector<unsigned> gen;
+  std::vector<char> live;
+  std::unordered_map<int, CellPlan> cell_plan;
+
+  // launch scratch
+  int* d_work = nullptr;
+  size_t work_cap = 0;
+  int* d_counters = nullptr;
+  size_t counters_cap = 0;
+  uint16_t* d_gl = nullptr;
+  size_t gl_cap = 0, gl_cap_elems = 0;
+  DevResult* d_results = nullptr;
+  size_t res_cap = 0;
+  int* d_idx = nullptr;
+  size_t idx_cap = 0;
+  DevResult* h_results = nullptr;
+  size_t h_results_cap = 0;
+  unsigned char* h_stage = nullptr;
+  size_t stage_cap = 0;
+
+  std::map<std::string, GraphEntry> graphs;
+  std::map<std::string, Variant> tuned;
+
+  // serving
+  std::thread serve_thread;
+  std::mutex serve_mu;
+  std::condition_variable serve_cv;
+  bool serving = false, serve_stop_flag = false, serve_drain = true;
+  mdeos_serve_config serve_cfg{};
+  std::deque<ServeQuery> serve_queue;
+  std::deque<ServeDone> serve_done;
+  std::unordered_map<long long, ServeCell> serve_cells;
+  mdeos_serve_stats serve_stats{};
+  long long next_ticket = 1;
+  double serve_t0 = 0.0;
+
+  ~Ctx();
+  mdeos_status init(const mdeos_config* cfg);
+  hipStream_t pick(void* stream) const;
+
+  mdeos_status ensure_atoms(int need);
+  mdeos_status ensure_cells(int need);
+  mdeos_status ensure_scratch(size_t work_n, size_t counters_n, size_t gl_bytes, size_t res_n);
+  mdeos_status ensure_stage(size_t bytes);
+  void graphs_clear();
+
+  void fill_record(CellRec& r, const mdeos_cell_spec& s, const mdeos_schedule& q, const CellPlan& p, int atom_off);
+  mdeos_handle handle_of(int slot) const;
+  int slot_of(mdeos_handle h) const;
+  mdeos_status alloc_cells(int n, const mdeos_cell_spec* specs, const mdeos_schedule& q, std::vector<int>& out);
+  void free_cells(const std::vector<int>& idx);
+  mdeos_status upload_records(const std::vector<int>& idx, hipStream_t s);
+  mdeos_status upload_state(int slot, const double* xyz, const double* v, hipStream_t s);
+  mdeos_status download_atoms(int slot, int which_mask, std::vector<double>& out, hipStream_t s);
+  mdeos_status download_record(int slot, CellRec& out, hipStream_t s);
+
+  bool choose_variant(const CellPlan& p, Variant& out) const;
+  std::string tune_key(const CellPlan& p) const;
+  void make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, int step_budget, bool sticky = false);
+  std::map<long long, Caps> sticky_caps;  // serving: bucket shapes only grow, so graphs are reused
+  mdeos_status run_buckets(std::vector<Bucket>& buckets, int step_budget, hipStream_t s, bool use_graph);
+  mdeos_status restrict_cells(const std::vector<int>& idx, mdeos_result* out, hipStream_t s);
+  AdvanceParams make_params(const Bucket& b, int bi, int step_budget);
+  mdeos_status fetch_results(int n, mdeos_result* out, hipStream_t s);
+  mdeos_status eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched, mdeos_result* out,
+                    hipStream_t s, bool plain);
+
+  // autotuner
+  void load_tune_cache();
+  void save_tune_cache();
+
+  // serving
+  void serve_loop();
+  void serve_shutdown();
+};
+
+}  // namespace mdeos

@@ -1,0 +1,87 @@
+"""The C-ABI library on the host: it loads, exports every declared entry point,
+validates queries and plans boxes without a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2508_06012_amd import mdeos as m
+from paper_2508_06012_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mdeos.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdeos_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = m.lib()
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(m.EXPORTED)
+
+
+def test_version_and_strerror():
+    assert "gfx950" in m.mdeos_version()
+    assert m.lib().mdeos_strerror(m.INVALID_ARG) == b"invalid argument"
+
+
+def spec(**kw):
+    d = dict(rho=0.8442, e=1.07, n_c=4, rc=2.5, dt=0.005, seed=1, cell_id=0)
+    d.update(kw)
+    return m.make_specs(d["rho"], d["e"], d["n_c"], d["rc"], d["dt"], d["seed"], d["cell_id"])[0]
+
+
+@pytest.mark.parametrize("bad", [dict(rho=0.0), dict(rho=-1.0), dict(e=0.0), dict(e=float("nan")), dict(n_c=0),
+                                 dict(n_c=11), dict(rc=0.0), dict(dt=0.0), dict(rc=7.0)])
+def test_invalid_specs_rejected(bad):
+    assert m.mdeos_validate(spec(**bad)) == m.INVALID_ARG
+
+
+@pytest.mark.parametrize("kw", [dict(n_steps=0, n_avg=1), dict(n_steps=100, n_avg=101), dict(n_steps=100, n_avg=50,
+                                n_blocks=7), dict(n_steps=100, n_avg=50, rescale_steps=(51,)),
+                                dict(n_steps=100, n_avg=50, energy_every=0), dict(n_steps=100, n_avg=50, n_blocks=1)])
+def test_invalid_schedules_rejected(kw):
+    d = dict(n_steps=100, n_avg=50, rescale_steps=(), n_blocks=10, energy_every=10)
+    d.update(kw)
+    s = m.make_schedule(d["n_steps"], d["n_avg"], d["rescale_steps"], d["n_blocks"], d["energy_every"])
+    assert m.mdeos_validate(spec(), s) == m.INVALID_ARG
+
+
+def test_valid_workload_cells_plan():
+    for w in (wl.cfg1(), wl.cfg2(mesh=16)):
+        specs, sch = m.specs_from_workload(w)
+        for i in range(len(specs)):
+            assert m.mdeos_validate(specs[i], sch) == m.OK
+            p = m.mdeos_plan(specs[i])
+            assert p.N == 4 * specs[i].n_c ** 3
+            assert p.L == pytest.approx(specs[i].n_c * (4 / specs[i].rho) ** (1 / 3), rel=1e-6)
+            assert p.rl > specs[i].rc and p.rl < p.L
+            assert p.lds_bytes <= 160 * 1024
+            assert p.list_cap % 8 == 0
+            # the extended box holds the real atoms plus their periodic images
+            assert p.ext_cap >= p.N
+
+
+def test_multi_image_flagged():
+    p = m.mdeos_plan(spec(rho=1.2, n_c=3, rc=3.0))
+    assert p.multi_image == 1
+    assert m.mdeos_plan(spec()).multi_image == 0
+
+
+def test_cell_bytes():
+    assert m.mdeos_cell_bytes(5) >= 500 * 48
+
+
+def test_create_without_device_fails_cleanly():
+    if m.mdeos_device_count() > 0:
+        pytest.skip("a device is present")
+    with pytest.raises(m.MdeosError) as e:
+        m.mdeos_create()
+    assert e.value.status == m.NO_DEVICE

@@ -88,8 +88,13 @@ typedef struct {
     double Epot_mean;  /* <E_pot> / N over energy steps in the window */
     double Ecold;      /* E_cold / N of the static lattice at rho */
     double drift;      /* (E(n) - E(n - n_avg)) / N */
+    double pairs;      /* ordered pairs within rc per step, averaged over energy steps */
     int n_samples;     /* samples averaged */
     int status;        /* MDEOS_CELL_* bits */
+    int n_builds;      /* neighbour-list builds */
+    int max_list;      /* largest neighbour count seen (capacity diagnostics) */
+    int max_ext;       /* largest real + ghost atom count seen */
+    int reserved;
 } mdeos_result;
 
 typedef struct {
@@ -180,6 +185,11 @@ mdeos_status mdeos_eval_plain(mdeos_ctx* ctx, int n, const mdeos_cell_spec* spec
                               mdeos_result* out, void* stream);
 
 mdeos_status mdeos_release(mdeos_ctx* ctx, int n, const mdeos_handle* h);
+
+/* Device time (ms, from HIP events on the launch stream) of the last
+ * persistent advance launch set of this context (all size buckets of one
+ * eval_batch / advance call), and the number of bucket launches in it. */
+mdeos_status mdeos_last_advance_time(mdeos_ctx* ctx, double* ms, int* n_launches);
 
 /* Copies a resident cell's state to the host: positions wrapped into [0, L),
  * velocities, and the number of steps completed. Any pointer may be NULL. */

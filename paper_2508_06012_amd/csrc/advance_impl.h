@@ -134,7 +134,9 @@ struct Box {
   float fx[APT], fy[APT], fz[APT], bx[APT], by[APT], bz[APT];
   float wi[APT];
   double ui[APT];
-  int gofs[APT], gmask[APT], nblk[APT];
+  int gofs[APT], gmask[APT], nblk[APT], cnt_in[APT];
+  double pairs_t;  // ordered in-range pairs of this thread's atoms over sampled steps
+  int esteps;      // sampled (energy) steps in this launch
 
   DEVI Box(const AdvanceParams& pp, unsigned char* l) : p(pp), lds(l) {
     lay = lds_layout(EXT, p.caps, LLDS);
@@ -411,10 +413,7 @@ struct Box {
     if (over) ctl->overflow = 1;
     __syncthreads();
     bool ok = ctl->overflow == 0;
-    if (t == 0) {
-      atomicMax(&c->max_ext, n_ext);
-      c->n_builds += 1;
-    }
+    if (t == 0) atomicMax(&c->max_ext, n_ext);
     ctl->n_ext = n_ext;
     return ok;
   }
@@ -446,6 +445,7 @@ struct Box {
       by[k] = (float)y[k];
       bz[k] = (float)z[k];
     }
+    if (t == 0) c->n_builds += 1;  // chunk-start reconstructions are not counted
     return build_lists();
   }
 
@@ -497,6 +497,7 @@ struct Box {
       fz[k] = az;
       wi[k] = w;
       ui[k] = ENERGY ? 4.0 * u - (double)cin * u_shift : 0.0;
+      cnt_in[k] = (ENERGY && a < N) ? cin : 0;
     }
   }
 
@@ -869,6 +870,8 @@ struct Box {
     const int RING = p.caps.ring;
     const float thr = 0.25f * (rl - sqrtf(rc2)) * (rl - sqrtf(rc2));  // (skin / 2)^2
     int pending = step + 1;  // first step not yet flushed
+    pairs_t = 0.0;
+    esteps = 0;
     __syncthreads();
     bool stopped = ctl->stop != 0;
     while (step < target && !stopped) {
@@ -907,8 +910,14 @@ struct Box {
       refresh_positions();
       __syncthreads();
       const bool energy = is_energy_step(k);
-      if (energy) forces<true>();
-      else forces<false>();
+      if (energy) {
+        forces<true>();
+#pragma unroll
+        for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
+        ++esteps;
+      } else {
+        forces<false>();
+      }
       double ka[APT], wa[APT], ua[APT];
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
@@ -965,6 +974,20 @@ struct Box {
     if (pending <= step) {
       flush(pending, step);
       __syncthreads();
+    }
+    {
+      double pa[APT], za[APT];
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        pa[q] = q == 0 ? pairs_t : 0.0;
+        za[q] = 0.0;
+      }
+      double P, z1, z2;
+      reduce_now(pa, za, za, P, z1, z2);
+      if (t == 0) {
+        c->pair_sum += P;
+        c->pair_steps += esteps;
+      }
     }
     store_state();
     const bool done = (step >= n) || stopped;

@@ -51,8 +51,13 @@ __global__ void k_restrict(const CellRec* cells, const int* idx, int n, DevResul
   if (st & (ST_NONFINITE | ST_OVERFLOW)) {
     r.P = r.P_se = r.P_rms = r.T = r.T_se = r.Epot_mean = r.drift = NAN;
   }
+  r.pairs = c.pair_steps > 0 ? c.pair_sum / c.pair_steps : 0.0;
   r.n_samples = done;
   r.status = st;
+  r.n_builds = c.n_builds;
+  r.max_list = c.max_list;
+  r.max_ext = c.max_ext;
+  r.pad = 0;
   out[i] = r;
 }
 

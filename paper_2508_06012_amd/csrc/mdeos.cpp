@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -67,10 +68,45 @@ static int pick_ext(int need) {
   return 0;
 }
 
-// Plans one cell: geometry, capacities and the LDS it needs.
+// Exact number of periodic images within rl of the faces for the FCC start
+// lattice: in half-lattice units the sites are (a, b, c) in [0, 2 n_c)^3 with
+// a + b + c even, at coordinate l (a / 2 + 1/4).
+static int lattice_ghosts(int n_c, double l, double L, double rl) {
+  const int m = 2 * n_c;
+  std::vector<int> img(m);
+  for (int a = 0; a < m; ++a) {
+    const double x = l * (0.5 * a + 0.25);
+    img[a] = 1 + (x < rl ? 1 : 0) + (x >= L - rl ? 1 : 0);
+  }
+  long g = 0;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      for (int c = 0; c < m; ++c)
+        if (((a + b + c) & 1) == 0) g += img[a] * img[b] * img[c] - 1;
+  return (int)g;
+}
+
+// Neighbours within rl of one site of the infinite FCC lattice (all images).
+static int lattice_neighbours(double l, double rl) {
+  const int k = (int)std::ceil(2.0 * rl / l) + 1;
+  int n = 0;
+  for (int i = -k; i <= k; ++i)
+    for (int j = -k; j <= k; ++j)
+      for (int q = -k; q <= k; ++q) {
+        if (((i + j + q) & 1) != 0 || (i == 0 && j == 0 && q == 0)) continue;
+        const double r2 = 0.25 * l * l * (double)(i * i + j * j + q * q);
+        if (r2 < (double)rl * rl) ++n;
+      }
+  return n;
+}
+
+// Plans one cell: geometry, capacities and the LDS it needs. Capacities cover
+// the start lattice exactly and the liquid with a margin; a cell that still
+// overflows is re-run with larger capacities by the batch paths.
 mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out) {
   if (skin <= 0.f) skin = 0.3f;
   const double L = box_length(s.n_c, s.rho);
+  const double l = std::cbrt(4.0 / s.rho);
   const int N = 4 * s.n_c * s.n_c * s.n_c;
   double sk = std::min<double>(skin, 0.5 * (L - s.rc));
   if (!(sk > 0.0)) return MDEOS_INVALID_ARG;
@@ -89,14 +125,21 @@ mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out) {
   out.nce = nce;
   out.ncell = nce * nce * nce;
   const double ghosts = s.rho * (ext_len * ext_len * ext_len - L * L * L);
-  out.ext_need = N + (int)std::ceil(1.15 * ghosts + 96.0);
+  const int g_lat = lattice_ghosts(s.n_c, l, L, (double)rl);
+  out.ext_need = N + std::max((int)std::ceil(1.15 * ghosts + 96.0), g_lat + 32);
   const double nl = 4.0 / 3.0 * M_PI * (double)rl * rl * rl * s.rho;
-  out.list_cap = align_up((int)std::ceil(1.25 * nl + 24.0), 8);
-  out.ext = pick_ext(out.ext_need);
+  const int n_lat = lattice_neighbours(l, (double)rl);
+  out.list_cap = align_up(std::max((int)std::ceil(1.25 * nl + 24.0), n_lat + 8), 8);
   out.multi_image = s.rc > 0.5 * L ? 1 : 0;
+  return finish_plan(out);
+}
+
+// Chooses the position stride and list location of a plan and its LDS bytes.
+mdeos_status finish_plan(CellPlan& out) {
+  out.ext = pick_ext(out.ext_need);
   if (out.ext == 0 || out.ncell > 65535) return MDEOS_INVALID_ARG;
   Caps c;
-  c.n_pad = align_up(N, 64);
+  c.n_pad = align_up(out.N, 64);
   c.list_cap = out.list_cap;
   c.ncell_cap = out.ncell;
   c.gmax = c.n_pad / 64;
@@ -501,48 +544,37 @@ static int variant_score(const Variant& v, int N) {
   return idle * 4 + (v.block == 512 ? 0 : 1);
 }
 
+static Caps caps_of(const CellPlan& p) {
+  Caps c;
+  c.n_pad = align_up(p.N, 64);
+  c.list_cap = p.list_cap;
+  c.ncell_cap = p.ncell;
+  c.gmax = c.n_pad / 64;
+  c.ring = ring_for(c.gmax);
+  return c;
+}
+
+// Picks the launch shape for a (merged) plan: a tuned choice if the tune cache
+// has one that fits, else the shape with the fewest idle threads, the
+// neighbour list in LDS when it fits there and the smallest position stride.
 bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
-  int best = -1;
-  int best_score = 1 << 30;
+  const Caps c = caps_of(p);
+  auto fits = [&](const Variant& v) {
+    return v.block * v.apt >= p.N && v.ext - 1 >= p.ext_need && lds_layout(v.ext, c, v.list_lds).total <= kLdsMax;
+  };
+  auto tv = tuned.find(tune_key(p));
+  if (tv != tuned.end() && variant_available(tv->second) && fits(tv->second)) {
+    out = tv->second;
+    return true;
+  }
+  int best = -1, best_score = 1 << 30;
   for (int i = 0; i < variant_count(); ++i) {
     Variant v = variant_at(i);
-    if (v.block * v.apt < p.N) continue;
-    if (v.ext - 1 < p.ext_need) continue;
-    if ((v.list_lds != 0) != (p.list_in_lds != 0)) continue;
-    Caps c;
-    c.n_pad = align_up(p.N, 64);
-    c.list_cap = p.list_cap;
-    c.ncell_cap = p.ncell;
-    c.gmax = c.n_pad / 64;
-    c.ring = ring_for(c.gmax);
-    if (lds_layout(v.ext, c, v.list_lds).total > kLdsMax) continue;
-    int sc = variant_score(v, p.N) + (v.ext - p.ext_need) / 512;
-    auto tv = tuned.find(tune_key(p));
-    if (tv != tuned.end() && tv->second.block == v.block && tv->second.apt == v.apt && tv->second.ext == v.ext &&
-        tv->second.list_lds == v.list_lds)
-      sc = -1;
+    if (!fits(v)) continue;
+    int sc = variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024;
     if (sc < best_score) {
       best_score = sc;
       best = i;
-    }
-  }
-  if (best < 0) {
-    // fall back to the device-memory list
-    for (int i = 0; i < variant_count(); ++i) {
-      Variant v = variant_at(i);
-      if (v.block * v.apt < p.N || v.ext - 1 < p.ext_need || v.list_lds) continue;
-      Caps c;
-      c.n_pad = align_up(p.N, 64);
-      c.list_cap = p.list_cap;
-      c.ncell_cap = p.ncell;
-      c.gmax = c.n_pad / 64;
-      c.ring = ring_for(c.gmax);
-      if (lds_layout(v.ext, c, false).total > kLdsMax) continue;
-      int sc = variant_score(v, p.N);
-      if (sc < best_score) {
-        best_score = sc;
-        best = i;
-      }
     }
   }
   if (best < 0) return false;
@@ -552,73 +584,68 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
 
 std::string Ctx::tune_key(const CellPlan& p) const {
   char buf[128];
-  int rho_bin = (int)std::floor(p.N / (p.Lw * p.Lw * p.Lw) * 10.0);
-  snprintf(buf, sizeof(buf), "gfx950/N%d/rl%.2f/rho%d", p.N, p.rl, rho_bin);
+  snprintf(buf, sizeof(buf), "gfx950/N%d/rl%.2f/ext%d/list%d/cells%d", p.N, p.rl, align_up(p.ext_need, 512),
+           align_up(p.list_cap, 16), align_up(p.ncell, 256));
   return buf;
 }
 
-// Groups cells into launches: same variant and LDS class; caps are maxima.
-// In sticky mode (serving) buckets are keyed by variant only, their caps only
-// grow and every variant seen before stays in the launch set (possibly with no
-// cells), so the launch set, and with it the captured graph, stays fixed while
-// the batch composition changes.
-static long long vkey(const Variant& v) {
-  return ((long long)v.block << 40) | ((long long)v.apt << 32) | ((long long)v.ext << 8) | v.list_lds;
+// Merged plan of a set of cells with one atom count: capacities are maxima.
+static CellPlan merge_plans(const std::vector<const CellPlan*>& ps) {
+  CellPlan m = *ps[0];
+  for (const CellPlan* p : ps) {
+    m.ext_need = std::max(m.ext_need, p->ext_need);
+    m.list_cap = std::max(m.list_cap, p->list_cap);
+    m.ncell = std::max(m.ncell, p->ncell);
+    m.rl = std::max(m.rl, p->rl);
+  }
+  return m;
 }
 
+// Groups cells into launches: one bucket per (atom count, cutoff) with
+// capacities that cover every cell in it; a bucket whose merged capacities do
+// not fit any launch shape is split by extended-box size. In sticky mode
+// (serving) the capacities of a bucket only grow and every bucket seen before
+// stays in the launch set (possibly without cells), so the launch set, and with
+// it the captured graph, stays fixed while the batch composition changes.
 void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, int step_budget, bool sticky) {
   (void)step_budget;
-  std::map<std::pair<long long, int>, Bucket> m;
+  std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int s : cells) {
     const CellPlan& p = cell_plan[s];
-    Variant v;
-    if (!choose_variant(p, v)) continue;  // cannot happen after plan_cell
-    int cls = sticky ? 0
-                     : (p.lds_bytes <= kLdsMax / 4 ? 4
-                        : p.lds_bytes <= kLdsMax / 3 ? 3
-                        : p.lds_bytes <= kLdsMax / 2 ? 2 : 1);
-    Bucket& b = m[{vkey(v), cls}];
-    b.v = v;
-    b.caps.n_pad = std::max(b.caps.n_pad, align_up(p.N, 64));
-    b.caps.list_cap = std::max(b.caps.list_cap, p.list_cap);
-    b.caps.ncell_cap = std::max(b.caps.ncell_cap, p.ncell);
-    b.cells.push_back(s);
+    groups[{p.N, (int)std::lround(h_cells[s].rc * 1000.0)}].push_back(s);
   }
-  if (sticky) {
-    for (auto& kv : sticky_caps) {
-      Variant v{(int)(kv.first >> 40), (int)((kv.first >> 32) & 0xff), (int)((kv.first >> 8) & 0xffffff),
-                (int)(kv.first & 0xff)};
-      Bucket& b = m[{kv.first, 0}];
-      b.v = v;
-      b.caps.n_pad = std::max(b.caps.n_pad, kv.second.n_pad);
-      b.caps.list_cap = std::max(b.caps.list_cap, kv.second.list_cap);
-      b.caps.ncell_cap = std::max(b.caps.ncell_cap, kv.second.ncell_cap);
-    }
-  }
+  if (sticky)
+    for (auto& kv : sticky_plans) groups[kv.first];  // keep every bucket seen before
   out.clear();
-  for (auto& kv : m) {
-    Bucket b = kv.second;
-    b.caps.gmax = b.caps.n_pad / 64;
-    b.caps.ring = ring_for(b.caps.gmax);
-    b.lds = lds_layout(b.v.ext, b.caps, b.v.list_lds).total;
-    if (b.lds > kLdsMax) {
-      // caps maxima from different cells overflow LDS: one launch per cell
-      for (int s : b.cells) {
-        Bucket one;
-        one.v = b.v;
-        const CellPlan& p = cell_plan[s];
-        one.caps.n_pad = align_up(p.N, 64);
-        one.caps.list_cap = p.list_cap;
-        one.caps.ncell_cap = p.ncell;
-        one.caps.gmax = one.caps.n_pad / 64;
-        one.caps.ring = ring_for(one.caps.gmax);
-        one.lds = lds_layout(one.v.ext, one.caps, one.v.list_lds).total;
-        one.cells.push_back(s);
-        out.push_back(one);
+  std::function<void(std::pair<int, int>, std::vector<int>&)> place = [&](std::pair<int, int> key,
+                                                                           std::vector<int>& cs) {
+    std::vector<const CellPlan*> ps;
+    for (int s : cs) ps.push_back(&cell_plan[s]);
+    CellPlan merged;
+    if (!ps.empty()) merged = merge_plans(ps);
+    if (sticky) {
+      auto it = sticky_plans.find(key);
+      if (it != sticky_plans.end()) {
+        if (ps.empty()) merged = it->second;
+        else merged = merge_plans({&merged, &it->second});
       }
-      continue;
     }
-    if (sticky) sticky_caps[vkey(b.v)] = b.caps;
+    if (ps.empty() && !sticky) return;
+    Variant v;
+    if (!choose_variant(merged, v)) {
+      if (cs.size() <= 1) return;  // cannot happen: every single plan fits
+      std::sort(cs.begin(), cs.end(), [&](int a, int b) { return cell_plan[a].ext_need < cell_plan[b].ext_need; });
+      std::vector<int> lo(cs.begin(), cs.begin() + cs.size() / 2), hi(cs.begin() + cs.size() / 2, cs.end());
+      place(key, lo);
+      place(key, hi);
+      return;
+    }
+    if (sticky) sticky_plans[key] = merged;
+    Bucket b;
+    b.v = v;
+    b.caps = caps_of(merged);
+    b.lds = lds_layout(v.ext, b.caps, v.list_lds).total;
+    b.cells = cs;
     // longest first
     std::stable_sort(b.cells.begin(), b.cells.end(), [&](int a, int c) {
       const CellPlan &pa = cell_plan[a], &pc = cell_plan[c];
@@ -626,8 +653,9 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
       double cc = (double)pc.N * pc.list_cap * (h_cells[c].n_steps - h_cells[c].step);
       return ca > cc;
     });
-    out.push_back(b);
-  }
+    out.push_back(std::move(b));
+  };
+  for (auto& kv : groups) place(kv.first, kv.second);
   for (Bucket& b : out) {
     int occ = std::max(1, occupancy(b.v, b.lds));
     b.grid = sticky ? occ * n_cu : std::max(1, std::min<int>((int)b.cells.size(), occ * n_cu));
@@ -692,8 +720,11 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
     return hipSuccess;
   };
 
+  HCHECK(hipEventRecord(ev_t0, s));
   if (!use_graph) {
     HCHECK(launch_all(s));
+    HCHECK(hipEventRecord(ev_t1, s));
+    timed_launches = (int)buckets.size();
     return MDEOS_OK;
   }
   auto it = graphs.find(key);
@@ -714,6 +745,8 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
     it = graphs.emplace(key, ge).first;
   }
   HCHECK(hipGraphLaunch(it->second.exec, s));
+  HCHECK(hipEventRecord(ev_t1, s));
+  timed_launches = (int)buckets.size();
   return MDEOS_OK;
 }
 
@@ -947,28 +980,55 @@ extern "C" mdeos_status mdeos_restrict(mdeos_ctx* ctx, int n, const mdeos_handle
   return MDEOS_OK;
 }
 
+// Runs lift + schedule + restrict for n cells (batched, or one launch per cell
+// for the plain path). Cells that overflowed a capacity are re-run from the
+// lift with larger capacities; capacities do not change a cell's arithmetic.
 mdeos_status Ctx::eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched, mdeos_result* out,
                        hipStream_t s, bool plain) {
   std::vector<int> idx;
   mdeos_status st = alloc_cells(n, specs, *sched, idx);
   if (st != MDEOS_OK) return st;
-  st = upload_records(idx, s);
-  if (st == MDEOS_OK) {
+  std::vector<int> pos(n);
+  for (int i = 0; i < n; ++i) pos[i] = i;
+  std::vector<int> todo = idx;
+  for (int attempt = 0; attempt < 3 && st == MDEOS_OK && !todo.empty(); ++attempt) {
+    st = upload_records(todo, s);
+    if (st != MDEOS_OK) break;
+    std::vector<mdeos_result> res(todo.size());
     if (!plain) {
       std::vector<Bucket> b;
-      make_buckets(idx, b, 0);
+      make_buckets(todo, b, 0);
       st = run_buckets(b, 0, s, true);
-      if (st == MDEOS_OK) st = restrict_cells(idx, out, s);
+      if (st == MDEOS_OK) st = restrict_cells(todo, res.data(), s);
     } else {
-      for (int i = 0; i < n && st == MDEOS_OK; ++i) {
-        std::vector<int> one{idx[i]};
+      for (size_t i = 0; i < todo.size() && st == MDEOS_OK; ++i) {
+        std::vector<int> one{todo[i]};
         std::vector<Bucket> b;
         make_buckets(one, b, 0);
         for (Bucket& q : b) q.grid = 1;
         st = run_buckets(b, 0, s, false);
-        if (st == MDEOS_OK) st = restrict_cells(one, out + i, s);
+        if (st == MDEOS_OK) st = restrict_cells(one, res.data() + i, s);
       }
     }
+    if (st != MDEOS_OK) break;
+    std::vector<int> again, again_pos;
+    for (size_t i = 0; i < todo.size(); ++i) {
+      out[pos[i]] = res[i];
+      if (!(res[i].status & MDEOS_CELL_OVERFLOW) || attempt == 2) continue;
+      const int slot = todo[i];
+      CellPlan p = cell_plan[slot];
+      p.ext_need = std::max(p.ext_need + p.ext_need / 2, res[i].max_ext + 64);
+      p.list_cap = align_up(std::max(p.list_cap + p.list_cap / 2, res[i].max_list + 16), 8);
+      if (finish_plan(p) != MDEOS_OK) continue;  // no larger launch shape: report the overflow
+      const CellRec old = h_cells[slot];
+      mdeos_cell_spec sp{old.rho, old.e, old.n_c, old.rc, old.dt, old.seed, old.cell_id};
+      fill_record(h_cells[slot], sp, *sched, p, old.atom_off);
+      cell_plan[slot] = p;
+      again.push_back(slot);
+      again_pos.push_back(pos[i]);
+    }
+    todo = again;
+    pos = again_pos;
   }
   free_cells(idx);
   return st;
@@ -1012,6 +1072,19 @@ extern "C" mdeos_status mdeos_release(mdeos_ctx* ctx, int n, const mdeos_handle*
 
 // Copies the selected arena arrays (bit k of which_mask = array k: x, y, z,
 // vx, vy, vz, fx, fy, fz, bx, by, bz) of one cell to out[k * N + i] as doubles.
+extern "C" mdeos_status mdeos_last_advance_time(mdeos_ctx* ctx, double* ms, int* n_launches) {
+  CTX_GUARD(C_(ctx));
+  Ctx* c = C_(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (c->timed_launches == 0) return set_error("no advance launch yet"), MDEOS_NOT_READY;
+  HCHECK(hipEventSynchronize(c->ev_t1));
+  float f = 0.f;
+  HCHECK(hipEventElapsedTime(&f, c->ev_t0, c->ev_t1));
+  if (ms) *ms = f;
+  if (n_launches) *n_launches = c->timed_launches;
+  return MDEOS_OK;
+}
+
 mdeos_status Ctx::download_atoms(int slot, int which_mask, std::vector<double>& out, hipStream_t s) {
   const CellRec& r = h_cells[slot];
   const int N = r.N;

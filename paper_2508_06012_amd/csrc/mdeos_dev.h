@@ -62,12 +62,16 @@ struct alignas(16) CellRec {
   int nU, pad0;
   double E_w0, E_n;
   double K, U, W;      // values of the last completed step
+  double pair_sum;     // ordered in-range pairs summed over sampled (energy) steps
+  int pair_steps;      // number of sampled steps
+  int pad1;
 };
 
 // Result in the layout of mdeos_result.
 struct DevResult {
   double P, P_se, P_rms, T, T_se, Epot_mean, Ecold, drift;
-  int n_samples, status;
+  double pairs;
+  int n_samples, status, n_builds, max_list, max_ext, pad;
 };
 
 // Structure-of-arrays atom state in device memory; each array has `cap` entries.

@@ -39,6 +39,7 @@ struct CellPlan {
 };
 
 mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out);
+mdeos_status finish_plan(CellPlan& out);
 
 // First-fit allocator of integer ranges with coalescing.
 class RangeAlloc {
@@ -181,7 +182,8 @@ struct Ctx {
   bool choose_variant(const CellPlan& p, Variant& out) const;
   std::string tune_key(const CellPlan& p) const;
   void make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, int step_budget, bool sticky = false);
-  std::map<long long, Caps> sticky_caps;  // serving: bucket shapes only grow, so graphs are reused
+  std::map<std::pair<int, int>, CellPlan> sticky_plans;  // serving: bucket capacities only grow
+  int timed_launches = 0;
   mdeos_status run_buckets(std::vector<Bucket>& buckets, int step_budget, hipStream_t s, bool use_graph);
   mdeos_status restrict_cells(const std::vector<int>& idx, mdeos_result* out, hipStream_t s);
   AdvanceParams make_params(const Bucket& b, int bi, int step_budget);

@@ -35,7 +35,8 @@ class Schedule(C.Structure):
 class Result(C.Structure):
     _fields_ = [("P", C.c_double), ("P_se", C.c_double), ("P_rms", C.c_double), ("T", C.c_double),
                 ("T_se", C.c_double), ("Epot_mean", C.c_double), ("Ecold", C.c_double), ("drift", C.c_double),
-                ("n_samples", C.c_int), ("status", C.c_int)]
+                ("pairs", C.c_double), ("n_samples", C.c_int), ("status", C.c_int), ("n_builds", C.c_int),
+                ("max_list", C.c_int), ("max_ext", C.c_int), ("reserved", C.c_int)]
 
 
 class Config(C.Structure):
@@ -61,15 +62,16 @@ class ServeStats(C.Structure):
 
 
 RESULT_DTYPE = np.dtype([("P", "f8"), ("P_se", "f8"), ("P_rms", "f8"), ("T", "f8"), ("T_se", "f8"),
-                         ("Epot_mean", "f8"), ("Ecold", "f8"), ("drift", "f8"), ("n_samples", "i4"),
-                         ("status", "i4")])
+                         ("Epot_mean", "f8"), ("Ecold", "f8"), ("drift", "f8"), ("pairs", "f8"),
+                         ("n_samples", "i4"), ("status", "i4"), ("n_builds", "i4"), ("max_list", "i4"),
+                         ("max_ext", "i4"), ("reserved", "i4")])
 assert RESULT_DTYPE.itemsize == C.sizeof(Result)
 
 EXPORTED = [
     "mdeos_strerror", "mdeos_last_error", "mdeos_version", "mdeos_validate", "mdeos_plan", "mdeos_cell_bytes",
     "mdeos_device_count", "mdeos_create", "mdeos_destroy", "mdeos_lift", "mdeos_lift_from_state",
     "mdeos_warm_start", "mdeos_advance", "mdeos_restrict", "mdeos_eval_batch", "mdeos_eval_plain",
-    "mdeos_release", "mdeos_state_export", "mdeos_debug_forces", "mdeos_debug_trajectory", "mdeos_serve_start",
+    "mdeos_release", "mdeos_last_advance_time", "mdeos_state_export", "mdeos_debug_forces", "mdeos_debug_trajectory", "mdeos_serve_start",
     "mdeos_serve_submit", "mdeos_serve_poll", "mdeos_serve_now", "mdeos_serve_stats_get", "mdeos_serve_stop",
 ]
 
@@ -115,6 +117,7 @@ def lib() -> C.CDLL:
     L.mdeos_eval_batch.argtypes = [vp, C.c_int, P(CellSpec), P(Schedule), P(Result), vp]
     L.mdeos_eval_plain.argtypes = [vp, C.c_int, P(CellSpec), P(Schedule), P(Result), vp]
     L.mdeos_release.argtypes = [vp, C.c_int, P(C.c_longlong)]
+    L.mdeos_last_advance_time.argtypes = [vp, dp, P(C.c_int)]
     L.mdeos_state_export.argtypes = [vp, C.c_longlong, dp, dp, P(C.c_int)]
     L.mdeos_debug_forces.argtypes = [vp, P(CellSpec), dp, dp, dp, dp]
     L.mdeos_debug_trajectory.argtypes = [vp, C.c_longlong, C.c_int, dp, dp, dp, dp]
@@ -293,6 +296,13 @@ def mdeos_eval_plain(ctx, specs, sched: Schedule, stream=None) -> np.ndarray:
 def mdeos_release(ctx, handles) -> None:
     hh = _handles(handles)
     _check(lib().mdeos_release(ctx, len(hh), hh), "mdeos_release")
+
+
+def mdeos_last_advance_time(ctx) -> tuple[float, int]:
+    ms = C.c_double()
+    n = C.c_int()
+    _check(lib().mdeos_last_advance_time(ctx, C.byref(ms), C.byref(n)), "mdeos_last_advance_time")
+    return ms.value, n.value
 
 
 def mdeos_state_export(ctx, handle: int, N: int):

@@ -3,7 +3,7 @@
 #include "variants.h"
 
 namespace mdeos {
-#define X(B, A, E, L) MDEOS_DEFINE_VARIANT(B, A, E, L)
+#define X(B, A, E, L, W) MDEOS_DEFINE_VARIANT(B, A, E, L, W)
 MDEOS_VARIANTS_A(X)
 #undef X
 }  // namespace mdeos

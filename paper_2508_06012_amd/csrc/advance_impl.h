@@ -79,15 +79,43 @@ DEVI double gauss(uint64_t seed, int64_t cell_id, int a, int c) {
   return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
 }
 
+// Cross-lane moves on the DPP network (no LDS traffic). CTRL codes:
+// 0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm [2,3,0,1] (lane ^ 2),
+// 0x141 row_half_mirror, 0x140 row_mirror.
+template <int CTRL>
+DEVI int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+DEVI double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v)), hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+DEVI double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of a double over the 64 lanes in a fixed tree (pairs, quads, eighths,
+// rows of 16, then the four rows); every lane gets the same value.
 DEVI double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 DEVI float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmaxf(v, __int_as_float(dpp_i<0xB1>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(dpp_i<0x4E>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(dpp_i<0x141>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(dpp_i<0x140>(__float_as_int(v))));
+  const float a = fmaxf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)),
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16)));
+  const float b = fmaxf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)),
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
+  return fmaxf(a, b);
 }
 DEVI int wave_max_i(int v) {
 #pragma unroll
@@ -287,18 +315,23 @@ struct Box {
   // image with shift +1 exists when the coordinate is below rl, -1 when it is
   // at least L - rl: exactly the images that fall in [-rl, L + rl).
   DEVI void write_images(double xx, double yy, double zz, int m, int g) {
+    // allowed shifts of each axis in ascending order: -1 (if any), 0, +1 (if any)
+    const int nfx = (m >> 1) & 1, nfy = (m >> 3) & 1, nfz = (m >> 5) & 1;
+    const int nx = 1 + (m & 1) + nfx, ny = 1 + ((m >> 2) & 1) + nfy, nz = 1 + ((m >> 4) & 1) + nfz;
 #pragma unroll 1
-    for (int sx = -1; sx <= 1; ++sx) {
-      if ((sx == 1 && !(m & 1)) || (sx == -1 && !(m & 2))) continue;
+    for (int ix = 0; ix < nx; ++ix) {
+      const int sx = ix - nfx;
+      const float X = (float)(xx + sx * Lw);
 #pragma unroll 1
-      for (int sy = -1; sy <= 1; ++sy) {
-        if ((sy == 1 && !(m & 4)) || (sy == -1 && !(m & 8))) continue;
+      for (int iy = 0; iy < ny; ++iy) {
+        const int sy = iy - nfy;
+        const float Y = (float)(yy + sy * Lw);
 #pragma unroll 1
-        for (int sz = -1; sz <= 1; ++sz) {
-          if ((sz == 1 && !(m & 16)) || (sz == -1 && !(m & 32))) continue;
-          if (sx == 0 && sy == 0 && sz == 0) continue;
-          PX(g) = (float)(xx + sx * Lw);
-          PY(g) = (float)(yy + sy * Lw);
+        for (int iz = 0; iz < nz; ++iz) {
+          const int sz = iz - nfz;
+          if ((sx | sy | sz) == 0) continue;
+          PX(g) = X;
+          PY(g) = Y;
           PZ(g) = (float)(zz + sz * Lw);
           ++g;
         }
@@ -562,7 +595,7 @@ struct Box {
       }
     }
     for (int s = 0; s < cnt; ++s) {
-      const double K = __shfl(Ks, s, 64), W = __shfl(Ws, s, 64), U = __shfl(Us, s, 64);
+      const double K = readlane_d(Ks, s), W = readlane_d(Ws, s), U = readlane_d(Us, s);
       const int k = k_first + s;
       observe(k, K, W, U, is_energy_step(k));
     }
@@ -891,6 +924,9 @@ struct Box {
           dm = fmaxf(dm, ex * ex + ey * ey + ez * ez);
         }
       }
+      // owners write their atoms and ghost images (the last barrier of the
+      // previous step ended every read of the old positions)
+      refresh_positions();
       dm = wave_max(dm);
       if (lane == 0) ctl->wmax[wv] = dm;
       __syncthreads();
@@ -898,7 +934,6 @@ struct Box {
 #pragma unroll
       for (int w = 0; w < NW; ++w) gm = fmaxf(gm, ctl->wmax[w]);
       if (gm > thr) {
-        __syncthreads();
         if (!rebuild()) {
           flush(pending, step);
           __syncthreads();
@@ -906,9 +941,9 @@ struct Box {
           if (t == 0) c->status |= ST_OVERFLOW;
           return;
         }
+        refresh_positions();
+        __syncthreads();
       }
-      refresh_positions();
-      __syncthreads();
       const bool energy = is_energy_step(k);
       if (energy) {
         forces<true>();
@@ -995,8 +1030,8 @@ struct Box {
   }
 };
 
-template <int BLOCK, int APT, int EXT, bool LLDS>
-__global__ void __launch_bounds__(BLOCK) k_advance(AdvanceParams p) {
+template <int BLOCK, int APT, int EXT, bool LLDS, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_advance(AdvanceParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
   Box<BLOCK, APT, EXT, LLDS> box(p, lds);
   if (threadIdx.x == 0) {
@@ -1020,20 +1055,20 @@ __global__ void __launch_bounds__(BLOCK) k_advance(AdvanceParams p) {
 }  // namespace
 
 // Host-side wrappers of one launch shape, defined in the variant translation units.
-#define MDEOS_DEFINE_VARIANT(B, A, E, L)                                                                   \
+#define MDEOS_DEFINE_VARIANT(B, A, E, L, W)                                                                \
   namespace variants {                                                                                    \
-  hipError_t launch_##B##_##A##_##E##_##L(const AdvanceParams& p, int grid, int lds, hipStream_t s) {      \
-    hipLaunchKernelGGL((k_advance<B, A, E, L != 0>), dim3(grid), dim3(B), lds, s, p);                      \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W(const AdvanceParams& p, int grid, int lds, hipStream_t s) { \
+    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W>), dim3(grid), dim3(B), lds, s, p);                  \
     return hipGetLastError();                                                                              \
   }                                                                                                       \
-  hipError_t attr_##B##_##A##_##E##_##L() {                                                               \
-    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0>,                                   \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W() {                                                         \
+    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W>,                                \
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                       \
   }                                                                                                       \
-  int occ_##B##_##A##_##E##_##L(int lds) {                                                                \
+  int occ_##B##_##A##_##E##_##L##_##W(int lds) {                                                          \
     int n = 0;                                                                                            \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0>, B, lds) != \
-        hipSuccess)                                                                                       \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0, W>, B,    \
+                                                     lds) != hipSuccess)                                  \
       n = 1;                                                                                              \
     return n;                                                                                             \
   }                                                                                                       \

@@ -7,10 +7,10 @@
 namespace mdeos {
 
 namespace variants {
-#define X(B, A, E, L)                                                                          \
-  hipError_t launch_##B##_##A##_##E##_##L(const AdvanceParams& p, int grid, int lds, hipStream_t s); \
-  hipError_t attr_##B##_##A##_##E##_##L();                                                     \
-  int occ_##B##_##A##_##E##_##L(int lds);
+#define X(B, A, E, L, W)                                                                                \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W(const AdvanceParams& p, int grid, int lds, hipStream_t s); \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W();                                                        \
+  int occ_##B##_##A##_##E##_##L##_##W(int lds);
 MDEOS_VARIANTS(X)
 #undef X
 }  // namespace variants
@@ -69,7 +69,7 @@ __global__ void k_zero_ints(int* p, int n) {
 }  // namespace
 
 static const Variant kVariants[] = {
-#define X(B, A, E, L) {B, A, E, L},
+#define X(B, A, E, L, W) {B, A, E, L, W},
     MDEOS_VARIANTS(X)
 #undef X
 };
@@ -79,14 +79,15 @@ Variant variant_at(int i) { return kVariants[i]; }
 
 bool variant_available(const Variant& v) {
   for (const Variant& w : kVariants)
-    if (w.block == v.block && w.apt == v.apt && w.ext == v.ext && w.list_lds == v.list_lds) return true;
+    if (w.block == v.block && w.apt == v.apt && w.ext == v.ext && w.list_lds == v.list_lds && w.wpe == v.wpe)
+      return true;
   return false;
 }
 
 hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, int lds_bytes, hipStream_t s) {
-#define X(B, A, E, L)                                                  \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L) \
-    return variants::launch_##B##_##A##_##E##_##L(p, grid, lds_bytes, s);
+#define X(B, A, E, L, W)                                                              \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W) \
+    return variants::launch_##B##_##A##_##E##_##L##_##W(p, grid, lds_bytes, s);
   MDEOS_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -94,17 +95,17 @@ hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, in
 
 hipError_t init_kernel_attributes() {
   hipError_t e = hipSuccess;
-#define X(B, A, E, L) \
-  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L();
+#define X(B, A, E, L, W) \
+  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W();
   MDEOS_VARIANTS(X)
 #undef X
   return e;
 }
 
 int occupancy(const Variant& v, int lds_bytes) {
-#define X(B, A, E, L)                                                  \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L) \
-    return variants::occ_##B##_##A##_##E##_##L(lds_bytes);
+#define X(B, A, E, L, W)                                                              \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W) \
+    return variants::occ_##B##_##A##_##E##_##L##_##W(lds_bytes);
   MDEOS_VARIANTS(X)
 #undef X
   return 1;

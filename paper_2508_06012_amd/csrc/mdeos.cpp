@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -63,7 +64,7 @@ namespace mdeos {
 double box_length(int n_c, double rho) { return n_c * std::cbrt(4.0 / rho); }
 
 static int pick_ext(int need) {
-  for (int e : {2048, 4096, 8176})
+  for (int e : {2048, 3072, 4096, 8176})
     if (need <= e - 1) return e;
   return 0;
 }
@@ -151,7 +152,7 @@ mdeos_status finish_plan(CellPlan& out) {
   return MDEOS_OK;
 }
 
-int ring_for(int gmax) { return std::max(2, std::min(32, 6144 / (24 * gmax))); }
+int ring_for(int gmax) { return std::max(2, std::min(16, 1536 / (24 * gmax))); }
 
 }  // namespace mdeos
 
@@ -281,6 +282,11 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     return MDEOS_DEVICE_ERROR;
   }
   load_tune_cache();
+  if (const char* fv = getenv("MDEOS_FORCE_VARIANT")) {
+    Variant v{};
+    if (sscanf(fv, "%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe) == 5 && variant_available(v))
+      forced_variant = v;
+  }
   return MDEOS_OK;
 }
 
@@ -562,6 +568,12 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
   auto fits = [&](const Variant& v) {
     return v.block * v.apt >= p.N && v.ext - 1 >= p.ext_need && lds_layout(v.ext, c, v.list_lds).total <= kLdsMax;
   };
+  if (forced_variant.block > 0) {
+    if (variant_available(forced_variant) && fits(forced_variant)) {
+      out = forced_variant;
+      return true;
+    }
+  }
   auto tv = tuned.find(tune_key(p));
   if (tv != tuned.end() && variant_available(tv->second) && fits(tv->second)) {
     out = tv->second;
@@ -571,7 +583,11 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
   for (int i = 0; i < variant_count(); ++i) {
     Variant v = variant_at(i);
     if (!fits(v)) continue;
-    int sc = variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024;
+    // waves per CU: registers allow wpe waves per SIMD; LDS allows whole boxes
+    const int lds = lds_layout(v.ext, c, v.list_lds).total;
+    const int wg_by_lds = kLdsMax / lds, wg_by_regs = std::max(1, 4 * v.wpe / (v.block / 64));
+    const int waves = std::min(wg_by_lds, wg_by_regs) * (v.block / 64);
+    int sc = -waves * 4096 + variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024;
     if (sc < best_score) {
       best_score = sc;
       best = i;

@@ -140,10 +140,10 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
 }
 
 // Kernel variants the library is built with (template arguments of the
-// advance kernel): threads per box, atoms per thread, position stride and
-// where the neighbour list lives.
+// advance kernel): threads per box, atoms per thread, position stride, where
+// the neighbour list lives, and the waves per SIMD the registers must allow.
 struct Variant {
-  int block, apt, ext, list_lds;
+  int block, apt, ext, list_lds, wpe;
 };
 
 // Host entry points implemented in kernels.hip.

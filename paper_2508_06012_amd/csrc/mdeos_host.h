@@ -145,6 +145,7 @@ struct Ctx {
 
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, Variant> tuned;
+  Variant forced_variant{0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe" (tuning)
 
   // serving
   std::thread serve_thread;

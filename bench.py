@@ -124,7 +124,7 @@ def main() -> int:
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-rate", type=float, default=10000.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -201,7 +201,7 @@ def main() -> int:
     }
     if not args.no_serve:
         print("# serving leg", file=sys.stderr, flush=True)
-        out["serving"] = serve_leg(m, wl, args.serve_rate, mesh=16, t_steps=8, seconds_cap=30.0)
+        out["serving"] = serve_leg(m, wl, args.serve_rate, mesh=32, t_steps=6, seconds_cap=30.0)
     if not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         cidx = np.linspace(0, n - 1, args.cpu_sample).astype(int)

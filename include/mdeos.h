@@ -100,7 +100,7 @@ typedef struct {
 typedef struct {
     int device;                /* HIP device ordinal */
     size_t hbm_budget;         /* bytes of resident cell state the context may hold; 0 = 64 GiB */
-    float skin;                /* Verlet skin; <= 0 selects 0.3 */
+    float skin;                /* Verlet skin; <= 0 selects 0.4 */
     int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
     const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
 } mdeos_config;

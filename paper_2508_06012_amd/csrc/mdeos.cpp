@@ -105,7 +105,7 @@ static int lattice_neighbours(double l, double rl) {
 // the start lattice exactly and the liquid with a margin; a cell that still
 // overflows is re-run with larger capacities by the batch paths.
 mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out) {
-  if (skin <= 0.f) skin = 0.3f;
+  if (skin <= 0.f) skin = 0.4f;
   const double L = box_length(s.n_c, s.rho);
   const double l = std::cbrt(4.0 / s.rho);
   const int N = 4 * s.n_c * s.n_c * s.n_c;
@@ -117,8 +117,10 @@ mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out) {
   out.L = (float)L;
   out.rl = rl;
   const double ext_len = L + 2.0 * rl;
+  // cells of edge >= rl/2 (5^3 stencil) unless that grid exceeds 1000 cells,
+  // then edge >= rl (3^3 stencil): keeps the binning arrays within 8 KB of LDS
   int R = 2, nce = (int)std::floor(ext_len * 2.0 / rl);
-  if ((long)nce * nce * nce > 4096) {
+  if ((long)nce * nce * nce > 1000) {
     R = 1;
     nce = (int)std::floor(ext_len / rl);
   }
@@ -256,7 +258,7 @@ void RangeAlloc::release_raw(int off, int n) {
 
 mdeos_status Ctx::init(const mdeos_config* cfg) {
   device = cfg ? cfg->device : 0;
-  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : 0.3f;
+  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : 0.4f;
   hbm_budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : (size_t)64 << 30;
   autotune = cfg ? cfg->autotune : 0;
   if (cfg && cfg->tune_cache) tune_cache = cfg->tune_cache;

@@ -129,7 +129,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: cells are independent and this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+              "(boxes are independent, so several GPUs would each take a share of them); run with --gpus 1", file=sys.stderr)
         return 2
 
     from paper_2508_06012_amd import mdeos as m

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmdeos.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["advance_a.hip", "advance_b.hip", "advance_c.hip", "advance_d.hip", "kernels.hip", "mdeos.cpp", "serve.cpp"]
+SOURCES = ["advance_a.hip", "advance_b.hip", "advance_c.hip", "advance_d.hip", "advance_e.hip", "kernels.hip", "mdeos.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -3,7 +3,7 @@
 #include "variants.h"
 
 namespace mdeos {
-#define X(B, A, E, L, W) MDEOS_DEFINE_VARIANT(B, A, E, L, W)
+#define X(B, A, E, L, W, M) MDEOS_DEFINE_VARIANT(B, A, E, L, W, M)
 MDEOS_VARIANTS_B(X)
 #undef X
 }  // namespace mdeos

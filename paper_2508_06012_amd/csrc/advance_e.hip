@@ -1,0 +1,9 @@
+// Instantiates the advance kernel for the launch shapes of group E.
+#include "advance_impl.h"
+#include "variants.h"
+
+namespace mdeos {
+#define X(B, A, E, L, W, M) MDEOS_DEFINE_VARIANT(B, A, E, L, W, M)
+MDEOS_VARIANTS_E(X)
+#undef X
+}  // namespace mdeos

@@ -20,6 +20,8 @@
 // and neighbour lists are built in a deterministic order, so a cell's bits do
 // not depend on the launch shape, the batch it runs in, or chunk boundaries.
 #pragma once
+#include <type_traits>
+
 #include "mdeos_dev.h"
 #include "mdeos_host.h"
 
@@ -131,15 +133,20 @@ DEVI double wrap1(double x, double L) {
   return x;
 }
 
-template <int BLOCK, int APT, int EXT, bool LLDS>
+// MI (minimum image): only the real atoms are held in LDS, binning cells
+// tile [0, L) periodically and every pair takes its nearest periodic image
+// (boxes with L >= 3 rl whose ghost-extended box would not fit in LDS).
+template <int BLOCK, int APT, int EXT, bool LLDS, bool MI>
 struct Box {
   static constexpr int NW = BLOCK / 64;
   static constexpr int SENT = EXT - 1;  // padding neighbour index
+  using PT = typename std::conditional<MI, double, float>::type;  // LDS position type
+  static constexpr int PB = sizeof(PT);
 
   const AdvanceParams& p;
   LdsLayout lay;
   unsigned char* lds;
-  float* px;  // py = px + EXT, pz = px + 2 EXT
+  PT* px;  // py = px + EXT, pz = px + 2 EXT
   uint16_t* list;  // [list_cap/8][n_pad][8]
   uint16_t *tmp, *sorted;
   int *cstart, *cfill, *scanbuf;
@@ -151,6 +158,7 @@ struct Box {
   CellRec* c;
   int N, G, n_pad, list_cap, ncell, nce, R;
   float L, rl, rl2, rc2, inv_ce;
+  double invLw;
   double Lw, dt, hdt;
   double V, Ndof, u_shift;
   double Ecold;  // total cold energy (uniform across the workgroup)
@@ -167,8 +175,8 @@ struct Box {
   int esteps;      // sampled (energy) steps in this launch
 
   DEVI Box(const AdvanceParams& pp, unsigned char* l) : p(pp), lds(l) {
-    lay = lds_layout(EXT, p.caps, LLDS);
-    px = (float*)(lds + lay.pos);
+    lay = lds_layout(EXT, p.caps, LLDS, MI);
+    px = (PT*)(lds + lay.pos);
     list = LLDS ? (uint16_t*)(lds + lay.list)
                 : p.gl_list + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
     tmp = (uint16_t*)(lds + lay.tmp);
@@ -186,9 +194,9 @@ struct Box {
     list_cap = p.caps.list_cap;
   }
 
-  DEVI float& PX(int j) { return px[j]; }
-  DEVI float& PY(int j) { return px[EXT + j]; }
-  DEVI float& PZ(int j) { return px[2 * EXT + j]; }
+  DEVI PT& PX(int j) { return px[j]; }
+  DEVI PT& PY(int j) { return px[EXT + j]; }
+  DEVI PT& PZ(int j) { return px[2 * EXT + j]; }
 
   DEVI void load_cell(int cidx) {
     c = p.cells + cidx;
@@ -204,7 +212,8 @@ struct Box {
     nce = c->nce;
     R = c->stencil;
     ncell = nce * nce * nce;
-    inv_ce = (float)nce / (L + 2.0f * rl);
+    inv_ce = MI ? (float)nce / L : (float)nce / (L + 2.0f * rl);
+    invLw = 1.0 / c->Lw;
     V = c->V;
     Ndof = 3.0 * N - 3.0;
     double irc2 = 1.0 / ((double)c->rc * (double)c->rc);
@@ -340,10 +349,15 @@ struct Box {
   }
 
   DEVI int cell_coord(float v) const {
-    int q = (int)floorf((v + rl) * inv_ce);
+    int q = (int)floorf((MI ? v : v + rl) * inv_ce);
     return min(max(q, 0), nce - 1);
   }
-  DEVI int cell_of(int e) { return (cell_coord(PZ(e)) * nce + cell_coord(PY(e))) * nce + cell_coord(PX(e)); }
+  DEVI int wrapc(int q) const { return q < 0 ? q + nce : (q >= nce ? q - nce : q); }
+  // nearest periodic image of a coordinate difference (FP64 positions)
+  DEVI double mimg(double d) const { return fma(-Lw, rint(d * invLw), d); }
+  DEVI int cell_of(int e) {
+    return (cell_coord((float)PZ(e)) * nce + cell_coord((float)PY(e))) * nce + cell_coord((float)PX(e));
+  }
 
   // Builds ghosts, the binning and every atom's neighbour list from the
   // build positions (bx, by, bz). Returns false on a capacity overflow.
@@ -357,12 +371,14 @@ struct Box {
         PX(a) = bx[k];
         PY(a) = by[k];
         PZ(a) = bz[k];
-        gmask[k] = ghost_mask(bx[k], by[k], bz[k]);
-        scanbuf[a] = n_images(gmask[k]);
+        if (!MI) {
+          gmask[k] = ghost_mask(bx[k], by[k], bz[k]);
+          scanbuf[a] = n_images(gmask[k]);
+        }
       }
     }
     __syncthreads();
-    int n_ghost = block_scan(scanbuf, N);
+    int n_ghost = MI ? 0 : block_scan(scanbuf, N);
     int n_ext = N + n_ghost;
     if (n_ext > SENT || ncell > p.caps.ncell_cap) {
       if (t == 0) atomicMax(&c->max_ext, n_ext);
@@ -371,7 +387,7 @@ struct Box {
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       int a = t + k * BLOCK;
-      if (a < N) {
+      if (a < N && !MI) {
         gofs[k] = N + scanbuf[a];
         write_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k], gofs[k]);
       }
@@ -407,7 +423,32 @@ struct Box {
     for (int k = 0; k < APT; ++k) {
       int a = t + k * BLOCK;
       int cnt = 0;
-      if (a < N) {
+      if (a < N && MI) {
+        // periodic stencil, one cell at a time (the grid has at least 2R+1 cells per edge)
+        const float xi = bx[k], yi = by[k], zi = bz[k];
+        const int cx = cell_coord(xi), cy = cell_coord(yi), cz = cell_coord(zi);
+        for (int dz = -R; dz <= R; ++dz) {
+          const int zz = wrapc(cz + dz);
+          for (int dy = -R; dy <= R; ++dy) {
+            const int yy = wrapc(cy + dy);
+            for (int dx = -R; dx <= R; ++dx) {
+              const int cq = (zz * nce + yy) * nce + wrapc(cx + dx);
+              const int lo = cstart[cq], hi = cstart[cq + 1];
+              for (int q = lo; q < hi; ++q) {
+                const int e = sorted[q];
+                const float ddx = (float)mimg((double)xi - (double)PX(e));
+                const float ddy = (float)mimg((double)yi - (double)PY(e));
+                const float ddz = (float)mimg((double)zi - (double)PZ(e));
+                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                if (r2 < rl2 && e != a) {
+                  if (cnt < list_cap) list[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)(PB * e);
+                  ++cnt;
+                }
+              }
+            }
+          }
+        }
+      } else if (a < N) {
         const float xi = bx[k], yi = by[k], zi = bz[k];
         const int cx = cell_coord(xi), cy = cell_coord(yi), cz = cell_coord(zi);
         const int x0 = max(cx - R, 0), x1 = min(cx + R, nce - 1);
@@ -437,10 +478,13 @@ struct Box {
       cm = min(cm, list_cap);
       int nb = __builtin_amdgcn_readfirstlane((cm + 7) >> 3);
       nblk[k] = nb;
-      // pad every lane of the wave (also atoms past N) to nb blocks
+      // pad every lane of the wave (also atoms past N) to nb blocks: with the
+      // far-away sentinel, or (minimum image, where no point is far from all
+      // atoms) with the atom itself, which the r^2 > 0 test drops
       if (a < n_pad) {
         int from = (a < N) ? min(cnt, list_cap) : 0;
-        for (int q = from; q < 8 * nb; ++q) list[(((q >> 3) * n_pad + a) << 3) + (q & 7)] = (uint16_t)(4 * SENT);
+        const uint16_t pad = (uint16_t)(PB * (MI ? (a < N ? a : SENT) : SENT));
+        for (int q = from; q < 8 * nb; ++q) list[(((q >> 3) * n_pad + a) << 3) + (q & 7)] = pad;
       }
     }
     if (over) ctl->overflow = 1;
@@ -457,9 +501,9 @@ struct Box {
     for (int k = 0; k < APT; ++k) {
       int a = t + k * BLOCK;
       if (a < N) {
-        PX(a) = (float)x[k];
-        PY(a) = (float)y[k];
-        PZ(a) = (float)z[k];
+        PX(a) = (PT)x[k];
+        PY(a) = (PT)y[k];
+        PZ(a) = (PT)z[k];
         if (gmask[k]) write_images(x[k], y[k], z[k], gmask[k], gofs[k]);
       }
     }
@@ -495,6 +539,7 @@ struct Box {
     for (int k = 0; k < APT; ++k) {
       const int a = t + k * BLOCK;
       const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
+      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
       float ax = 0.f, ay = 0.f, az = 0.f, w = 0.f;
       double u = 0.0;  // pair energies are summed in FP64 (energy steps only)
       int cin = 0;
@@ -506,10 +551,20 @@ struct Box {
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
             const uint32_t off = (m & 1) ? (wd[m >> 1] >> 16) : (wd[m >> 1] & 0xffffu);
-            const float* q = reinterpret_cast<const float*>(pb + off);
-            const float dx = xi - q[0], dy = yi - q[EXT], dz = zi - q[2 * EXT];
+            const PT* q = reinterpret_cast<const PT*>(pb + off);
+            float dx, dy, dz;
+            if (MI) {
+              // image-corrected difference in FP64, then FP32 pair math
+              dx = (float)mimg(xi64 - q[0]);
+              dy = (float)mimg(yi64 - q[EXT]);
+              dz = (float)mimg(zi64 - q[2 * EXT]);
+            } else {
+              dx = xi - q[0];
+              dy = yi - q[EXT];
+              dz = zi - q[2 * EXT];
+            }
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool in = r2 < rc2;
+            const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
             const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
             const float ir6 = ir2 * ir2 * ir2;
             const float vir = fmaf(48.0f, ir6, -24.0f) * ir6;
@@ -1030,10 +1085,10 @@ struct Box {
   }
 };
 
-template <int BLOCK, int APT, int EXT, bool LLDS, int WPE>
+template <int BLOCK, int APT, int EXT, bool LLDS, int WPE, bool MI>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_advance(AdvanceParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
-  Box<BLOCK, APT, EXT, LLDS> box(p, lds);
+  Box<BLOCK, APT, EXT, LLDS, MI> box(p, lds);
   if (threadIdx.x == 0) {
     box.PX(EXT - 1) = kSentinelPos;
     box.PY(EXT - 1) = kSentinelPos;
@@ -1055,19 +1110,19 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
 }  // namespace
 
 // Host-side wrappers of one launch shape, defined in the variant translation units.
-#define MDEOS_DEFINE_VARIANT(B, A, E, L, W)                                                                \
+#define MDEOS_DEFINE_VARIANT(B, A, E, L, W, M)                                                                \
   namespace variants {                                                                                    \
-  hipError_t launch_##B##_##A##_##E##_##L##_##W(const AdvanceParams& p, int grid, int lds, hipStream_t s) { \
-    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W>), dim3(grid), dim3(B), lds, s, p);                  \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M(const AdvanceParams& p, int grid, int lds, hipStream_t s) { \
+    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W, M != 0>), dim3(grid), dim3(B), lds, s, p);                  \
     return hipGetLastError();                                                                              \
   }                                                                                                       \
-  hipError_t attr_##B##_##A##_##E##_##L##_##W() {                                                         \
-    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W>,                                \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M() {                                                         \
+    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W, M != 0>,                                \
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                       \
   }                                                                                                       \
-  int occ_##B##_##A##_##E##_##L##_##W(int lds) {                                                          \
+  int occ_##B##_##A##_##E##_##L##_##W##_##M(int lds) {                                                          \
     int n = 0;                                                                                            \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0, W>, B,    \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0, W, M != 0>, B,    \
                                                      lds) != hipSuccess)                                  \
       n = 1;                                                                                              \
     return n;                                                                                             \

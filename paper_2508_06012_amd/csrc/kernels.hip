@@ -7,10 +7,10 @@
 namespace mdeos {
 
 namespace variants {
-#define X(B, A, E, L, W)                                                                                \
-  hipError_t launch_##B##_##A##_##E##_##L##_##W(const AdvanceParams& p, int grid, int lds, hipStream_t s); \
-  hipError_t attr_##B##_##A##_##E##_##L##_##W();                                                        \
-  int occ_##B##_##A##_##E##_##L##_##W(int lds);
+#define X(B, A, E, L, W, M)                                                                                  \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M(const AdvanceParams& p, int grid, int lds, hipStream_t s); \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M();                                                        \
+  int occ_##B##_##A##_##E##_##L##_##W##_##M(int lds);
 MDEOS_VARIANTS(X)
 #undef X
 }  // namespace variants
@@ -69,7 +69,7 @@ __global__ void k_zero_ints(int* p, int n) {
 }  // namespace
 
 static const Variant kVariants[] = {
-#define X(B, A, E, L, W) {B, A, E, L, W},
+#define X(B, A, E, L, W, M) {B, A, E, L, W, M},
     MDEOS_VARIANTS(X)
 #undef X
 };
@@ -79,15 +79,16 @@ Variant variant_at(int i) { return kVariants[i]; }
 
 bool variant_available(const Variant& v) {
   for (const Variant& w : kVariants)
-    if (w.block == v.block && w.apt == v.apt && w.ext == v.ext && w.list_lds == v.list_lds && w.wpe == v.wpe)
+    if (w.block == v.block && w.apt == v.apt && w.ext == v.ext && w.list_lds == v.list_lds && w.wpe == v.wpe &&
+        w.mi == v.mi)
       return true;
   return false;
 }
 
 hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, int lds_bytes, hipStream_t s) {
-#define X(B, A, E, L, W)                                                              \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W) \
-    return variants::launch_##B##_##A##_##E##_##L##_##W(p, grid, lds_bytes, s);
+#define X(B, A, E, L, W, M)                                                                      \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M) \
+    return variants::launch_##B##_##A##_##E##_##L##_##W##_##M(p, grid, lds_bytes, s);
   MDEOS_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -95,17 +96,17 @@ hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, in
 
 hipError_t init_kernel_attributes() {
   hipError_t e = hipSuccess;
-#define X(B, A, E, L, W) \
-  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W();
+#define X(B, A, E, L, W, M) \
+  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W##_##M();
   MDEOS_VARIANTS(X)
 #undef X
   return e;
 }
 
 int occupancy(const Variant& v, int lds_bytes) {
-#define X(B, A, E, L, W)                                                              \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W) \
-    return variants::occ_##B##_##A##_##E##_##L##_##W(lds_bytes);
+#define X(B, A, E, L, W, M)                                                                      \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M) \
+    return variants::occ_##B##_##A##_##E##_##L##_##W##_##M(lds_bytes);
   MDEOS_VARIANTS(X)
 #undef X
   return 1;

@@ -134,12 +134,30 @@ mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out) {
   const int n_lat = lattice_neighbours(l, (double)rl);
   out.list_cap = align_up(std::max((int)std::ceil(1.25 * nl + 24.0), n_lat + 8), 8);
   out.multi_image = s.rc > 0.5 * L ? 1 : 0;
+  out.minimg = 0;
+  if (finish_plan(out) == MDEOS_OK) return MDEOS_OK;
+  // the ghost-extended box does not fit: minimum image over the real atoms
+  // (needs at least three binning cells of edge >= rl per box edge)
+  CellPlan mi = out;
+  mi.minimg = 1;
+  mi.multi_image = 0;
+  int Rm = 2, ncm = (int)std::floor(2.0 * L / rl);
+  if ((long)ncm * ncm * ncm > 1000 || ncm < 5) {
+    Rm = 1;
+    ncm = (int)std::floor(L / rl);
+  }
+  if (ncm < 3) return MDEOS_INVALID_ARG;
+  mi.stencil = Rm;
+  mi.nce = ncm;
+  mi.ncell = ncm * ncm * ncm;
+  mi.ext_need = N + 1;
+  out = mi;
   return finish_plan(out);
 }
 
 // Chooses the position stride and list location of a plan and its LDS bytes.
 mdeos_status finish_plan(CellPlan& out) {
-  out.ext = pick_ext(out.ext_need);
+  out.ext = out.minimg ? (out.ext_need <= 4087 ? 4088 : 0) : pick_ext(out.ext_need);
   if (out.ext == 0 || out.ncell > 65535) return MDEOS_INVALID_ARG;
   Caps c;
   c.n_pad = align_up(out.N, 64);
@@ -147,7 +165,7 @@ mdeos_status finish_plan(CellPlan& out) {
   c.ncell_cap = out.ncell;
   c.gmax = c.n_pad / 64;
   c.ring = ring_for(c.gmax);
-  LdsLayout with = lds_layout(out.ext, c, true), without = lds_layout(out.ext, c, false);
+  LdsLayout with = lds_layout(out.ext, c, true, out.minimg), without = lds_layout(out.ext, c, false, out.minimg);
   out.list_in_lds = with.total <= kLdsMax ? 1 : 0;
   out.lds_bytes = out.list_in_lds ? with.total : without.total;
   if (out.lds_bytes > kLdsMax) return MDEOS_INVALID_ARG;
@@ -286,7 +304,8 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   load_tune_cache();
   if (const char* fv = getenv("MDEOS_FORCE_VARIANT")) {
     Variant v{};
-    if (sscanf(fv, "%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe) == 5 && variant_available(v))
+    if (sscanf(fv, "%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi) == 6 &&
+        variant_available(v))
       forced_variant = v;
   }
   return MDEOS_OK;
@@ -568,7 +587,8 @@ static Caps caps_of(const CellPlan& p) {
 bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
   const Caps c = caps_of(p);
   auto fits = [&](const Variant& v) {
-    return v.block * v.apt >= p.N && v.ext - 1 >= p.ext_need && lds_layout(v.ext, c, v.list_lds).total <= kLdsMax;
+    return v.mi == p.minimg && v.block * v.apt >= p.N && v.ext - 1 >= p.ext_need &&
+           lds_layout(v.ext, c, v.list_lds, v.mi).total <= kLdsMax;
   };
   if (forced_variant.block > 0) {
     if (variant_available(forced_variant) && fits(forced_variant)) {
@@ -586,7 +606,7 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
     Variant v = variant_at(i);
     if (!fits(v)) continue;
     // waves per CU: registers allow wpe waves per SIMD; LDS allows whole boxes
-    const int lds = lds_layout(v.ext, c, v.list_lds).total;
+    const int lds = lds_layout(v.ext, c, v.list_lds, v.mi).total;
     const int wg_by_lds = kLdsMax / lds, wg_by_regs = std::max(1, 4 * v.wpe / (v.block / 64));
     const int waves = std::min(wg_by_lds, wg_by_regs) * (v.block / 64);
     int sc = -waves * 4096 + variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024;
@@ -602,14 +622,14 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
 
 std::string Ctx::tune_key(const CellPlan& p) const {
   char buf[128];
-  snprintf(buf, sizeof(buf), "gfx950/N%d/rl%.2f/ext%d/list%d/cells%d", p.N, p.rl, align_up(p.ext_need, 512),
-           align_up(p.list_cap, 16), align_up(p.ncell, 256));
+  snprintf(buf, sizeof(buf), "gfx950/N%d/rl%.2f/ext%d/list%d/cells%d/mi%d", p.N, p.rl, align_up(p.ext_need, 512),
+           align_up(p.list_cap, 16), align_up(p.ncell, 256), p.minimg);
   return buf;
 }
 
 // Merged plan of a set of cells with one atom count: capacities are maxima.
 static CellPlan merge_plans(const std::vector<const CellPlan*>& ps) {
-  CellPlan m = *ps[0];
+  CellPlan m = *ps[0];  // all plans of a bucket share N and the image method
   for (const CellPlan* p : ps) {
     m.ext_need = std::max(m.ext_need, p->ext_need);
     m.list_cap = std::max(m.list_cap, p->list_cap);
@@ -630,7 +650,7 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int s : cells) {
     const CellPlan& p = cell_plan[s];
-    groups[{p.N, (int)std::lround(h_cells[s].rc * 1000.0)}].push_back(s);
+    groups[{p.N * 2 + p.minimg, (int)std::lround(h_cells[s].rc * 1000.0)}].push_back(s);
   }
   if (sticky)
     for (auto& kv : sticky_plans) groups[kv.first];  // keep every bucket seen before
@@ -662,7 +682,7 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
     Bucket b;
     b.v = v;
     b.caps = caps_of(merged);
-    b.lds = lds_layout(v.ext, b.caps, v.list_lds).total;
+    b.lds = lds_layout(v.ext, b.caps, v.list_lds, v.mi).total;
     b.cells = cs;
     // longest first
     std::stable_sort(b.cells.begin(), b.cells.end(), [&](int a, int c) {

@@ -104,9 +104,11 @@ struct AdvanceParams {
 
 // LDS layout of one box. EXT is the stride of each position array (compile
 // time), so the three coordinates of neighbour j sit at byte offsets
-// 4j, 4j + 4 EXT and 4j + 8 EXT and one VGPR address serves all three loads.
+// s j, s (j + EXT) and s (j + 2 EXT) (s = 4 for float, 8 for the FP64
+// positions of the minimum-image variant) and one VGPR address serves all
+// three loads.
 struct LdsLayout {
-  int pos;        // float[3][EXT]
+  int pos;        // float[3][EXT] (double[3][EXT] for minimum image)
   int list;       // uint16[list_cap/8][n_pad][8] (when the list lives in LDS)
   int tmp;        // uint16[EXT]   (the ghost-count scan uses tmp..sorted as int[N])
   int sorted;     // uint16[EXT]
@@ -120,10 +122,10 @@ struct LdsLayout {
 
 __host__ __device__ inline int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
-__host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool list_in_lds) {
+__host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool list_in_lds, bool mi = false) {
   LdsLayout l;
   int o = 0;
-  l.pos = o; o += 12 * ext;
+  l.pos = o; o += (mi ? 24 : 12) * ext;
   l.list = o; o += list_in_lds ? 2 * c.list_cap * c.n_pad : 0;
   o = align_up(o, 16);
   l.tmp = o; o += 2 * ext;
@@ -141,9 +143,10 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
 
 // Kernel variants the library is built with (template arguments of the
 // advance kernel): threads per box, atoms per thread, position stride, where
-// the neighbour list lives, and the waves per SIMD the registers must allow.
+// the neighbour list lives, the waves per SIMD the registers must allow, and
+// minimum image (no ghosts) for large boxes.
 struct Variant {
-  int block, apt, ext, list_lds, wpe;
+  int block, apt, ext, list_lds, wpe, mi;
 };
 
 // Host entry points implemented in kernels.hip.

@@ -36,6 +36,7 @@ struct CellPlan {
   int list_in_lds = 0;
   int lds_bytes = 0;
   int multi_image = 0;
+  int minimg = 0;  // 1: minimum-image variant (no ghosts)
 };
 
 mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out);
@@ -145,7 +146,7 @@ struct Ctx {
 
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, Variant> tuned;
-  Variant forced_variant{0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe" (tuning)
+  Variant forced_variant{0, 0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe,mi" (tuning)
 
   // serving
   std::thread serve_thread;

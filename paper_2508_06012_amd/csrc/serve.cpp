@@ -48,7 +48,8 @@ void Ctx::load_tune_cache() {
     size_t lb = s.find('[', j), rb = s.find(']', j);
     if (lb == std::string::npos || rb == std::string::npos) break;
     Variant v{};
-    if (sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe) == 5 &&
+    if (sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d , %d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe,
+               &v.mi) == 6 &&
         variant_available(v))
       tuned[key] = v;
     i = rb + 1;
@@ -65,7 +66,8 @@ void Ctx::save_tune_cache() {
     size_t k = 0;
     for (auto& kv : tuned) {
       f << "  \"" << kv.first << "\": [" << kv.second.block << ", " << kv.second.apt << ", " << kv.second.ext << ", "
-        << kv.second.list_lds << ", " << kv.second.wpe << "]" << (++k < tuned.size() ? "," : "") << "\n";
+        << kv.second.list_lds << ", " << kv.second.wpe << ", " << kv.second.mi << "]"
+        << (++k < tuned.size() ? "," : "") << "\n";
     }
     f << "}\n";
   }

@@ -128,7 +128,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: cells are independent and this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(boxes are independent, so several GPUs would each take a share of them); run with --gpus 1", file=sys.stderr)
         return 2
 

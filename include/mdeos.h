@@ -103,7 +103,13 @@ typedef struct {
     float skin;                /* Verlet skin; <= 0 selects 0.4 */
     int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
     const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
+    int precision;             /* how each atom sums its pair energies and virials (forces are FP32):
+                                  MDEOS_PREC_FP64 (default) or MDEOS_PREC_KAHAN */
 } mdeos_config;
+
+/* Per-atom accumulation of pair energy and virial terms. The box sums that
+ * follow are FP64 in both modes. */
+enum { MDEOS_PREC_FP64 = 0, MDEOS_PREC_KAHAN = 1 };
 
 typedef struct mdeos_ctx mdeos_ctx;
 typedef long long mdeos_handle;

@@ -136,6 +136,9 @@ DEVI double wrap1(double x, double L) {
 // MI (minimum image): only the real atoms are held in LDS, binning cells
 // tile [0, L) periodically and every pair takes its nearest periodic image
 // (boxes with L >= 3 rl whose ghost-extended box would not fit in LDS).
+// What the pair loop sums per atom besides the force.
+enum { ACC_F = 0, ACC_FW = 1, ACC_FWU = 2 };
+
 template <int BLOCK, int APT, int EXT, bool LLDS, bool MI>
 struct Box {
   static constexpr int NW = BLOCK / 64;
@@ -162,14 +165,14 @@ struct Box {
   double Lw, dt, hdt;
   double V, Ndof, u_shift;
   double Ecold;  // total cold energy (uniform across the workgroup)
+  bool kahan;    // per-atom energy/virial sums in compensated FP32 (uniform)
 
   // owned atoms: a = t + k BLOCK
   // state in FP64 (positions unwrapped since the last list build), forces and
   // build positions in FP32
   double x[APT], y[APT], z[APT], vx[APT], vy[APT], vz[APT];
   float fx[APT], fy[APT], fz[APT], bx[APT], by[APT], bz[APT];
-  float wi[APT];
-  double ui[APT];
+  double wi[APT], ui[APT];
   int gofs[APT], gmask[APT], nblk[APT], cnt_in[APT];
   double pairs_t;  // ordered in-range pairs of this thread's atoms over sampled steps
   int esteps;      // sampled (energy) steps in this launch
@@ -192,6 +195,7 @@ struct Box {
     wv = t >> 6;
     n_pad = p.caps.n_pad;
     list_cap = p.caps.list_cap;
+    kahan = p.kahan != 0;
   }
 
   DEVI PT& PX(int j) { return px[j]; }
@@ -531,8 +535,12 @@ struct Box {
   //   f_ij = 24 r^-2 r^-6 (2 r^-6 - 1) d, pair virial r.f = 24 r^-6 (2 r^-6 - 1),
   //   energy 4 r^-6 (r^-6 - 1) - 4 (rc^-12 - rc^-6).
   // Neighbours between rc and rl and the padding entries add exact zeros.
-  template <bool ENERGY>
-  DEVI void forces() {
+  // ACC selects what else is summed per atom besides the FP32 force:
+  // ACC_F nothing, ACC_FW the virial, ACC_FWU virial, energy and the in-range
+  // pair count. KAHAN sums virial and energy in FP32 with Kahan compensation,
+  // otherwise each term is promoted and summed in FP64.
+  template <int ACC, bool KAHAN>
+  DEVI void forces_impl() {
     const uint4* lb = reinterpret_cast<const uint4*>(list);
     const char* pb = reinterpret_cast<const char*>(px);
 #pragma unroll
@@ -540,17 +548,18 @@ struct Box {
       const int a = t + k * BLOCK;
       const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
       const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
-      float ax = 0.f, ay = 0.f, az = 0.f, w = 0.f;
-      double u = 0.0;  // pair energies are summed in FP64 (energy steps only)
+      float ax = 0.f, ay = 0.f, az = 0.f;
+      double wd = 0.0, ud = 0.0;                  // FP64 sums
+      float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;  // Kahan sums and compensations
       int cin = 0;
       const int nb = nblk[k];
       if (a < n_pad) {
         for (int b = 0; b < nb; ++b) {
           const uint4 ent = lb[b * n_pad + a];
-          const uint32_t wd[4] = {ent.x, ent.y, ent.z, ent.w};
+          const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
-            const uint32_t off = (m & 1) ? (wd[m >> 1] >> 16) : (wd[m >> 1] & 0xffffu);
+            const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
             const PT* q = reinterpret_cast<const PT*>(pb + off);
             float dx, dy, dz;
             if (MI) {
@@ -569,12 +578,27 @@ struct Box {
             const float ir6 = ir2 * ir2 * ir2;
             const float vir = fmaf(48.0f, ir6, -24.0f) * ir6;
             const float ff = vir * ir2;
-            w += vir;
             ax = fmaf(ff, dx, ax);
             ay = fmaf(ff, dy, ay);
             az = fmaf(ff, dz, az);
-            if (ENERGY) {
-              u += (double)fmaf(ir6, ir6, -ir6);
+            if (ACC >= ACC_FW) {
+              if (KAHAN) {
+                const float y1 = vir - wc, t1 = ws + y1;
+                wc = (t1 - ws) - y1;
+                ws = t1;
+              } else {
+                wd += (double)vir;
+              }
+            }
+            if (ACC == ACC_FWU) {
+              const float e = fmaf(ir6, ir6, -ir6);
+              if (KAHAN) {
+                const float y2 = e - uc, t2 = us + y2;
+                uc = (t2 - us) - y2;
+                us = t2;
+              } else {
+                ud += (double)e;
+              }
               cin += in ? 1 : 0;
             }
           }
@@ -583,10 +607,21 @@ struct Box {
       fx[k] = ax;
       fy[k] = ay;
       fz[k] = az;
-      wi[k] = w;
-      ui[k] = ENERGY ? 4.0 * u - (double)cin * u_shift : 0.0;
-      cnt_in[k] = (ENERGY && a < N) ? cin : 0;
+      if (KAHAN) {
+        wd = (double)ws - (double)wc;
+        ud = (double)us - (double)uc;
+      }
+      wi[k] = ACC >= ACC_FW ? wd : 0.0;
+      ui[k] = ACC == ACC_FWU ? 4.0 * ud - (double)cin * u_shift : 0.0;
+      cnt_in[k] = (ACC == ACC_FWU && a < N) ? cin : 0;
     }
+  }
+  template <int ACC>
+  DEVI void forces() {
+    if (kahan)
+      forces_impl<ACC, true>();
+    else
+      forces_impl<ACC, false>();
   }
 
   // --- per-step bookkeeping (FP64) --------------------------------------------------
@@ -757,13 +792,13 @@ struct Box {
     if (!rebuild()) return false;
     refresh_positions();
     __syncthreads();
-    forces<true>();
+    forces<ACC_FWU>();
     double ua[APT], wa[APT], za[APT];
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       bool v = valid(k);
       ua[k] = v ? ui[k] : 0.0;
-      wa[k] = v ? (double)wi[k] : 0.0;
+      wa[k] = v ? wi[k] : 0.0;
       za[k] = 0.0;
     }
     double zz;
@@ -1001,12 +1036,14 @@ struct Box {
       }
       const bool energy = is_energy_step(k);
       if (energy) {
-        forces<true>();
+        forces<ACC_FWU>();
 #pragma unroll
         for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
         ++esteps;
+      } else if (k > c->n_steps - c->n_avg || c->debug_energy) {
+        forces<ACC_FW>();  // the virial enters P only inside the averaging window
       } else {
-        forces<false>();
+        forces<ACC_F>();
       }
       double ka[APT], wa[APT], ua[APT];
 #pragma unroll
@@ -1016,7 +1053,7 @@ struct Box {
         vz[q] = fma(hdt, (double)fz[q], vz[q]);
         const bool v = valid(q);
         ka[q] = v ? 0.5 * (vx[q] * vx[q] + vy[q] * vy[q] + vz[q] * vz[q]) : 0.0;
-        wa[q] = v ? 0.5 * (double)wi[q] : 0.0;
+        wa[q] = v ? 0.5 * wi[q] : 0.0;
         ua[q] = (v && energy) ? 0.5 * ui[q] : 0.0;
       }
       group_sums(ka, wa, ua, ring + (size_t)(k % RING) * 3 * p.caps.gmax);

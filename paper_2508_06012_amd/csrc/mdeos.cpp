@@ -280,6 +280,11 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   hbm_budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : (size_t)64 << 30;
   autotune = cfg ? cfg->autotune : 0;
   if (cfg && cfg->tune_cache) tune_cache = cfg->tune_cache;
+  precision = cfg ? cfg->precision : MDEOS_PREC_FP64;
+  if (precision != MDEOS_PREC_FP64 && precision != MDEOS_PREC_KAHAN) {
+    set_error("precision must be MDEOS_PREC_FP64 or MDEOS_PREC_KAHAN");
+    return MDEOS_INVALID_ARG;
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0) {
     set_error("no HIP device");
@@ -289,6 +294,8 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   hipDeviceProp_t prop;
   HCHECK(hipGetDeviceProperties(&prop, device));
   n_cu = prop.multiProcessorCount;
+  arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
   HCHECK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
   for (int i = 0; i < kAux; ++i) {
     HCHECK(hipStreamCreateWithFlags(&aux[i], hipStreamNonBlocking));
@@ -581,49 +588,114 @@ static Caps caps_of(const CellPlan& p) {
   return c;
 }
 
-// Picks the launch shape for a (merged) plan: a tuned choice if the tune cache
-// has one that fits, else the shape with the fewest idle threads, the
-// neighbour list in LDS when it fits there and the smallest position stride.
-bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
+// Every launch shape that fits a (merged) plan, best first by a static model:
+// most resident waves per CU (registers allow wpe waves per SIMD, LDS allows
+// whole boxes), then the fewest idle threads, the neighbour list in LDS, the
+// smallest position stride.
+int Ctx::rank_variants(const CellPlan& p, std::vector<Variant>& out) const {
   const Caps c = caps_of(p);
+  std::vector<std::pair<int, int>> scored;
+  for (int i = 0; i < variant_count(); ++i) {
+    const Variant v = variant_at(i);
+    const int lds = lds_layout(v.ext, c, v.list_lds, v.mi).total;
+    if (v.mi != p.minimg || v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax) continue;
+    const int wg_by_lds = kLdsMax / lds, wg_by_regs = std::max(1, 4 * v.wpe / (v.block / 64));
+    const int waves = std::min(wg_by_lds, wg_by_regs) * (v.block / 64);
+    scored.push_back({-waves * 4096 + variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024, i});
+  }
+  std::stable_sort(scored.begin(), scored.end());
+  out.clear();
+  for (auto& sc : scored) out.push_back(variant_at(sc.second));
+  return (int)out.size();
+}
+
+// Picks the launch shape for a (merged) plan: a forced shape, else a tuned
+// one if the tune cache has one that fits, else the best by the static model.
+bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
+  std::vector<Variant> ranked;
+  if (rank_variants(p, ranked) == 0) return false;
   auto fits = [&](const Variant& v) {
-    return v.mi == p.minimg && v.block * v.apt >= p.N && v.ext - 1 >= p.ext_need &&
-           lds_layout(v.ext, c, v.list_lds, v.mi).total <= kLdsMax;
+    for (const Variant& r : ranked)
+      if (r.block == v.block && r.apt == v.apt && r.ext == v.ext && r.list_lds == v.list_lds && r.wpe == v.wpe &&
+          r.mi == v.mi)
+        return true;
+    return false;
   };
-  if (forced_variant.block > 0) {
-    if (variant_available(forced_variant) && fits(forced_variant)) {
-      out = forced_variant;
-      return true;
-    }
+  if (forced_variant.block > 0 && fits(forced_variant)) {
+    out = forced_variant;
+    return true;
   }
   auto tv = tuned.find(tune_key(p));
-  if (tv != tuned.end() && variant_available(tv->second) && fits(tv->second)) {
+  if (tv != tuned.end() && fits(tv->second)) {
     out = tv->second;
     return true;
   }
-  int best = -1, best_score = 1 << 30;
-  for (int i = 0; i < variant_count(); ++i) {
-    Variant v = variant_at(i);
-    if (!fits(v)) continue;
-    // waves per CU: registers allow wpe waves per SIMD; LDS allows whole boxes
-    const int lds = lds_layout(v.ext, c, v.list_lds, v.mi).total;
-    const int wg_by_lds = kLdsMax / lds, wg_by_regs = std::max(1, 4 * v.wpe / (v.block / 64));
-    const int waves = std::min(wg_by_lds, wg_by_regs) * (v.block / 64);
-    int sc = -waves * 4096 + variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024;
-    if (sc < best_score) {
-      best_score = sc;
-      best = i;
-    }
-  }
-  if (best < 0) return false;
-  out = variant_at(best);
+  out = ranked[0];
   return true;
+}
+
+// Online autotuning of launch shapes. A cell's results do not depend on the
+// launch shape or on chunk boundaries (bit for bit), so candidate shapes are
+// timed on successive chunks of the batch's own work and nothing is
+// recomputed: one untimed chunk (lift and the first steps), then kTuneRounds
+// rounds of one kTuneSteps chunk per candidate, the bucket alone on the
+// device. The fastest (minimum over rounds) is kept under the bucket's tune
+// key and written to the tune cache.
+static constexpr int kTuneSteps = 40, kTuneRounds = 2, kTuneMaxCand = 6, kTuneMinCells = 64;
+
+mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) {
+  bool changed = false;
+  for (Bucket& b : buckets) {
+    if (forced_variant.block > 0 || (int)b.cells.size() < kTuneMinCells) continue;
+    const std::string key = tune_key(b.plan);
+    if (tuned.count(key)) continue;
+    std::vector<Variant> cand;
+    rank_variants(b.plan, cand);
+    if ((int)cand.size() > kTuneMaxCand) cand.resize(kTuneMaxCand);
+    if (cand.size() < 2) {
+      if (!cand.empty()) tuned[key] = cand[0], changed = true;
+      continue;
+    }
+    int left = 1 << 30;
+    for (int c : b.cells) left = std::min(left, h_cells[c].n_steps - h_cells[c].step);
+    if (left < (1 + kTuneRounds * (int)cand.size()) * kTuneSteps + 1) continue;
+    std::vector<Bucket> one{b};
+    auto use = [&](const Variant& v) {
+      one[0].v = v;
+      one[0].lds = lds_layout(v.ext, one[0].caps, v.list_lds, v.mi).total;
+      one[0].grid = std::max(1, std::min<int>((int)b.cells.size(), std::max(1, occupancy(v, one[0].lds)) * n_cu));
+    };
+    use(b.v);
+    mdeos_status st = run_buckets(one, kTuneSteps, s, false);
+    if (st != MDEOS_OK) return st;
+    std::vector<float> best(cand.size(), 1e30f);
+    for (int r = 0; r < kTuneRounds; ++r) {
+      for (size_t i = 0; i < cand.size(); ++i) {
+        use(cand[i]);
+        st = run_buckets(one, kTuneSteps, s, false);
+        if (st != MDEOS_OK) return st;
+        HCHECK(hipEventSynchronize(ev_t1));
+        float ms = 0.f;
+        HCHECK(hipEventElapsedTime(&ms, ev_t0, ev_t1));
+        best[i] = std::min(best[i], ms);
+      }
+    }
+    const size_t w = std::min_element(best.begin(), best.end()) - best.begin();
+    tuned[key] = cand[w];
+    changed = true;
+    b.v = cand[w];
+    b.lds = lds_layout(b.v.ext, b.caps, b.v.list_lds, b.v.mi).total;
+    b.grid = std::max(1, std::min<int>((int)b.cells.size(), std::max(1, occupancy(b.v, b.lds)) * n_cu));
+    ++tune_runs;
+  }
+  if (changed) save_tune_cache();
+  return MDEOS_OK;
 }
 
 std::string Ctx::tune_key(const CellPlan& p) const {
   char buf[128];
-  snprintf(buf, sizeof(buf), "gfx950/N%d/rl%.2f/ext%d/list%d/cells%d/mi%d", p.N, p.rl, align_up(p.ext_need, 512),
-           align_up(p.list_cap, 16), align_up(p.ncell, 256), p.minimg);
+  snprintf(buf, sizeof(buf), "%s/N%d/rl%.2f/ext%d/list%d/cells%d/mi%d/prec%d", arch.c_str(), p.N, p.rl,
+           align_up(p.ext_need, 512), align_up(p.list_cap, 16), align_up(p.ncell, 256), p.minimg, precision);
   return buf;
 }
 
@@ -681,6 +753,7 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
     if (sticky) sticky_plans[key] = merged;
     Bucket b;
     b.v = v;
+    b.plan = merged;
     b.caps = caps_of(merged);
     b.lds = lds_layout(v.ext, b.caps, v.list_lds, v.mi).total;
     b.cells = cs;
@@ -809,6 +882,7 @@ AdvanceParams Ctx::make_params(const Bucket& b, int bi, int step_budget) {
   p.a = arena;
   p.gl_list = b.v.list_lds ? nullptr : d_gl + b.gl_off / 2;
   p.caps = b.caps;
+  p.kahan = precision == MDEOS_PREC_KAHAN ? 1 : 0;
   return p;
 }
 
@@ -1036,7 +1110,8 @@ mdeos_status Ctx::eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule
     if (!plain) {
       std::vector<Bucket> b;
       make_buckets(todo, b, 0);
-      st = run_buckets(b, 0, s, true);
+      if (autotune) st = autotune_buckets(b, s);
+      if (st == MDEOS_OK) st = run_buckets(b, 0, s, true);
       if (st == MDEOS_OK) st = restrict_cells(todo, res.data(), s);
     } else {
       for (size_t i = 0; i < todo.size() && st == MDEOS_OK; ++i) {

@@ -100,6 +100,7 @@ struct AdvanceParams {
   AtomArena a;
   uint16_t* gl_list;    // device-memory neighbour lists (per workgroup), or null
   Caps caps;
+  int kahan;            // 1: Kahan-compensated FP32 per-atom energy/virial sums, 0: FP64
 };
 
 // LDS layout of one box. EXT is the stride of each position array (compile

@@ -69,6 +69,7 @@ struct Bucket {
   int work_off = 0;
   size_t gl_off = 0;
   std::vector<int> cells;
+  CellPlan plan{};  // merged capacities of the cells (what the launch shape must fit)
 };
 
 struct GraphEntry {
@@ -106,6 +107,9 @@ struct Ctx {
   float skin = 0.3f;
   size_t hbm_budget = 0;
   int autotune = 0;
+  int tune_runs = 0;  // buckets timed by the autotuner so far
+  int precision = MDEOS_PREC_FP64;
+  std::string arch = "gfx950";  // device architecture (tune-cache key)
   std::string tune_cache;
   std::recursive_mutex mu;
 
@@ -182,6 +186,8 @@ struct Ctx {
   mdeos_status download_record(int slot, CellRec& out, hipStream_t s);
 
   bool choose_variant(const CellPlan& p, Variant& out) const;
+  int rank_variants(const CellPlan& p, std::vector<Variant>& out) const;
+  mdeos_status autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s);
   std::string tune_key(const CellPlan& p) const;
   void make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, int step_budget, bool sticky = false);
   std::map<std::pair<int, int>, CellPlan> sticky_plans;  // serving: bucket capacities only grow

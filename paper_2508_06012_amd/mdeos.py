@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmdeos.so")
 
 OK, INVALID_ARG, OUT_OF_MEMORY, DEVICE_ERROR, NOT_READY, ADMISSION_FULL, NO_DEVICE = 0, -1, -2, -3, -4, -5, -6
 CELL_NONFINITE, CELL_ENERGY_BELOW_COLD, CELL_DRIFT, CELL_OVERFLOW, CELL_COLD_RELIFT = 1, 2, 4, 8, 16
+PREC_FP64, PREC_KAHAN = 0, 1
 MAX_RESCALE = 8
 
 
@@ -41,7 +42,8 @@ class Result(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget", C.c_size_t), ("skin", C.c_float), ("autotune", C.c_int),
-                ("tune_cache", C.c_char_p)]
+                ("tune_cache", C.c_char_p),
+                ("precision", C.c_int)]
 
 
 class PlanInfo(C.Structure):
@@ -174,9 +176,11 @@ def make_schedule(n_steps: int, n_avg: int, rescale_steps=(), n_blocks: int = 10
     return s
 
 
-def make_specs(rho, e, n_c, rc, dt, seed: int, cell_id) -> C.Array:
+def make_specs(rho, e, n_c, rc, dt, seed, cell_id) -> C.Array:
+    """Array of cell specs; every argument is a scalar or has one entry per cell."""
     rho = np.atleast_1d(np.asarray(rho, dtype=float))
     n = rho.size
+    seeds = np.broadcast_to(np.asarray(seed, dtype=object), (n,))
     e = np.broadcast_to(np.asarray(e, dtype=float), (n,))
     n_c = np.broadcast_to(np.asarray(n_c, dtype=int), (n,))
     rc = np.broadcast_to(np.asarray(rc, dtype=float), (n,))
@@ -185,7 +189,7 @@ def make_specs(rho, e, n_c, rc, dt, seed: int, cell_id) -> C.Array:
     arr = (CellSpec * n)()
     for i in range(n):
         arr[i] = CellSpec(float(rho[i]), float(e[i]), int(n_c[i]), float(rc[i]), float(dt[i]),
-                          int(seed) & (2 ** 64 - 1), int(cid[i]))
+                          int(seeds[i]) & (2 ** 64 - 1), int(cid[i]))
     return arr
 
 
@@ -224,8 +228,8 @@ def mdeos_cell_bytes(n_c: int) -> int:
 
 
 def mdeos_create(device: int = 0, hbm_budget: int = 0, skin: float = 0.0, autotune: int = 0,
-                 tune_cache: str | None = None) -> C.c_void_p:
-    cfg = Config(device, hbm_budget, skin, autotune, tune_cache.encode() if tune_cache else None)
+                 tune_cache: str | None = None, precision: int = 0) -> C.c_void_p:
+    cfg = Config(device, hbm_budget, skin, autotune, tune_cache.encode() if tune_cache else None, precision)
     ctx = C.c_void_p()
     _check(lib().mdeos_create(C.byref(cfg), C.byref(ctx)), "mdeos_create")
     return ctx

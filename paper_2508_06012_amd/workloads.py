@@ -173,6 +173,23 @@ def cfg5(seed: int = DEFAULT_SEED, n: int = 65_536) -> Workload:
     )
 
 
+def stratified_sample(w: Workload, n_rho: int = 8, n_T: int = 8) -> np.ndarray:
+    """Indices of a fixed stratified subsample: the lowest-index cell in each
+    of n_rho x n_T equal bins over the workload's density and temperature
+    ranges (bins with no cell are skipped)."""
+    lo_r, hi_r = w.rho.min(), w.rho.max()
+    lo_t, hi_t = w.T.min(), w.T.max()
+    br = np.minimum(((w.rho - lo_r) / (hi_r - lo_r) * n_rho).astype(int), n_rho - 1)
+    bt = np.minimum(((w.T - lo_t) / (hi_t - lo_t) * n_T).astype(int), n_T - 1)
+    out = []
+    for i in range(n_rho):
+        for j in range(n_T):
+            idx = np.nonzero((br == i) & (bt == j))[0]
+            if idx.size:
+                out.append(int(idx[0]))
+    return np.array(out, dtype=int)
+
+
 @dataclass
 class Query:
     t_arrival: float

@@ -85,3 +85,21 @@ def test_create_without_device_fails_cleanly():
     with pytest.raises(m.MdeosError) as e:
         m.mdeos_create()
     assert e.value.status == m.NO_DEVICE
+
+
+def test_create_rejects_unknown_precision():
+    # checked before any device call, so this runs on the CPU too
+    with pytest.raises(m.MdeosError) as e:
+        m.mdeos_create(precision=7)
+    assert e.value.status == m.INVALID_ARG
+    assert "precision" in str(e.value)
+
+
+def test_config_layout_matches_header():
+    """The binding's config struct lists the header's fields in order."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "mdeos.h")).read()
+    end = hdr.index("} mdeos_config;")
+    body = hdr[hdr.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    names = re.findall(r"\b(\w+);", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+    assert names == [f[0] for f in m.Config._fields_]

@@ -1,5 +1,6 @@
-"""Full-size uneven (108..4000 atoms, rc 2.5/3.0) and large-cutoff (rc 4.0)
-batches on the GPU, checked against the oracle on sampled cells.
+"""Full-size uneven batch (108..4000 atoms, rc 2.5/3.0) and minimum-image
+boxes on the GPU, checked against the oracle on sampled cells. (The rc = 4.0
+large batch is covered, in both accumulation modes, by test_gpu_precision.)
 
 Deterministic checks (forces, energies) use the per-step bars of
 test_gpu_parity. Time averages of chaotic trajectories are compared through
@@ -132,16 +133,3 @@ def test_uneven_batch_full_size(ctx):
     # averages must at least be finite and physical
     big = w.N >= 1372
     assert np.isfinite(res["P"][big]).all() and (res["T"][big] > 0).all()
-
-
-def test_large_cutoff_batch_full_size(ctx):
-    """All 65,536 cells of 864 atoms at rc = 4; oracle on 8 sampled cells."""
-    w = wl.cfg5()
-    specs, sch = m.specs_from_workload(w)
-    print("large batch of 65536", flush=True)
-    res = m.mdeos_eval_batch(ctx, specs, sch)
-    bad = (res["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)) != 0
-    assert not bad.any(), np.nonzero(bad)
-    pick = list(np.linspace(0, w.n - 1, 8).astype(int))
-    o = oracle_many([ocell(w, i) for i in pick], w.sched)
-    check_stats([res[i] for i in pick], o, "large", [f"cell {i} rho {w.rho[i]:.3f}" for i in pick])

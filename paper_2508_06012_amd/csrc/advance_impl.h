@@ -553,55 +553,74 @@ struct Box {
       float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;  // Kahan sums and compensations
       int cin = 0;
       const int nb = nblk[k];
-      if (a < n_pad) {
-        for (int b = 0; b < nb; ++b) {
-          const uint4 ent = lb[b * n_pad + a];
-          const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
+      // one block of 8 list entries (two 16-bit byte offsets per word)
+      auto block = [&](const uint4 ent) __attribute__((always_inline)) {
+        const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
 #pragma unroll
-          for (int m = 0; m < 8; ++m) {
-            const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
-            const PT* q = reinterpret_cast<const PT*>(pb + off);
-            float dx, dy, dz;
-            if (MI) {
-              // image-corrected difference in FP64, then FP32 pair math
-              dx = (float)mimg(xi64 - q[0]);
-              dy = (float)mimg(yi64 - q[EXT]);
-              dz = (float)mimg(zi64 - q[2 * EXT]);
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
+          const PT* q = reinterpret_cast<const PT*>(pb + off);
+          float dx, dy, dz;
+          if (MI) {
+            // image-corrected difference in FP64, then FP32 pair math
+            dx = (float)mimg(xi64 - q[0]);
+            dy = (float)mimg(yi64 - q[EXT]);
+            dz = (float)mimg(zi64 - q[2 * EXT]);
+          } else {
+            dx = xi - q[0];
+            dy = yi - q[EXT];
+            dz = zi - q[2 * EXT];
+          }
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
+          const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
+          const float ir6 = ir2 * ir2 * ir2;
+          const float vir = fmaf(48.0f, ir6, -24.0f) * ir6;
+          const float ff = vir * ir2;
+          ax = fmaf(ff, dx, ax);
+          ay = fmaf(ff, dy, ay);
+          az = fmaf(ff, dz, az);
+          if (ACC >= ACC_FW) {
+            if (KAHAN) {
+              const float y1 = vir - wc, t1 = ws + y1;
+              wc = (t1 - ws) - y1;
+              ws = t1;
             } else {
-              dx = xi - q[0];
-              dy = yi - q[EXT];
-              dz = zi - q[2 * EXT];
-            }
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
-            const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
-            const float ir6 = ir2 * ir2 * ir2;
-            const float vir = fmaf(48.0f, ir6, -24.0f) * ir6;
-            const float ff = vir * ir2;
-            ax = fmaf(ff, dx, ax);
-            ay = fmaf(ff, dy, ay);
-            az = fmaf(ff, dz, az);
-            if (ACC >= ACC_FW) {
-              if (KAHAN) {
-                const float y1 = vir - wc, t1 = ws + y1;
-                wc = (t1 - ws) - y1;
-                ws = t1;
-              } else {
-                wd += (double)vir;
-              }
-            }
-            if (ACC == ACC_FWU) {
-              const float e = fmaf(ir6, ir6, -ir6);
-              if (KAHAN) {
-                const float y2 = e - uc, t2 = us + y2;
-                uc = (t2 - us) - y2;
-                us = t2;
-              } else {
-                ud += (double)e;
-              }
-              cin += in ? 1 : 0;
+              wd += (double)vir;
             }
           }
+          if (ACC == ACC_FWU) {
+            const float e = fmaf(ir6, ir6, -ir6);
+            if (KAHAN) {
+              const float y2 = e - uc, t2 = us + y2;
+              uc = (t2 - us) - y2;
+              us = t2;
+            } else {
+              ud += (double)e;
+            }
+            cin += in ? 1 : 0;
+          }
+        }
+      };
+      if (a < n_pad && nb > 0) {
+        // Blocks are loaded one ahead into two alternating registers, so a
+        // block's load latency (device memory when the list does not fit in
+        // LDS) overlaps the arithmetic of the block before it.
+        // The loads are unconditional (the index is clamped to the last
+        // block, nb - 1 < list_cap / 8), so the wait before a block only
+        // covers the load issued before it.
+        // The scheduling barriers keep each load where it is issued (the
+        // scheduler would otherwise sink it next to its use).
+        const uint4* row = lb + a;
+        uint4 e0 = row[0];
+        for (int b = 0; b < nb; b += 2) {
+          const uint4 e1 = row[min(b + 1, nb - 1) * n_pad];
+          __builtin_amdgcn_sched_barrier(0);
+          block(e0);
+          if (b + 1 >= nb) break;
+          e0 = row[min(b + 2, nb - 1) * n_pad];
+          __builtin_amdgcn_sched_barrier(0);
+          block(e1);
         }
       }
       fx[k] = ax;

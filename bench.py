@@ -9,15 +9,27 @@ lift + advance + restrict, inputs prepared on the host. Prints one JSON line.
 
 Beside the headline (EOS evaluations per second of the batched path) it
 reports atom-steps/s, the plain path (one cell per launch, cells one after
-another) on a stratified sample, the force kernel against the FP32 roofline
-(algorithmic FLOPs from the measured ordered in-range pair counts, kernel time
-from HIP events on the launch stream), a short serving run with p50/p99 query
-latency, and the FP64 oracle timed on this host's cores on a bounded sample,
-whose results are also compared with the GPU's (statistical parity).
+another) on a stratified sample, the single-cell latency of the 256-atom
+case, the force kernel against the FP32 roofline (algorithmic FLOPs from the
+measured ordered in-range pair counts, kernel time from HIP events on the
+launch stream, HBM traffic from a committed counter summary while the kernel
+sources are unchanged), a short serving run with p50/p99 query latency, and
+the FP64 oracle timed on this host's cores on a bounded sample, whose results
+are also compared with the GPU's (statistical parity).
+
+Launch shapes are autotuned during the warmup steps (results do not depend
+on them). --workload cfg3 / cfg5 and --precision kahan run the other batch
+workloads and the Kahan accumulation mode with the same accounting.
+
+Profile summaries (profiles/) are written from rocprofv3 output by
+--trace-summary and --pmc-summary (see each summary for its commands).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -31,6 +43,38 @@ PEAK_FP32 = 157.3          # TFLOP/s, MI355X FP32 vector (packed) spec
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s, 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 FLOP_PAIR = 23             # per ordered in-range pair: force + virial
 FLOP_PAIR_ENERGY = 5       # extra on energy steps
+HERE = os.path.dirname(os.path.abspath(__file__))
+ADVANCE = "k_advance"      # the dominant kernel (name prefix in traces)
+PROFILE_NAME = {"cfg2": "uniform_4096x500", "cfg3": "uneven_10000", "cfg5": "large_65536x864"}
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of every source that shapes the device work (kernels, host planning, ABI)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(HERE, "paper_2508_06012_amd", "csrc", "*")))
+    files.append(os.path.join(HERE, "include", "mdeos.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from_profile(workload: str, precision: str, profiles: str = os.path.join(HERE, "profiles")):
+    """HBM bytes per advance launch from the committed counter summary, or
+    None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(profiles, f"{ADVANCE}_{PROFILE_NAME.get(workload, workload)}_{precision}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- `"):
+                k, v = line[3:].split("`", 1)
+                vals[k] = v.split(":", 1)[1].strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def energy_steps(s) -> int:
@@ -114,22 +158,145 @@ def serve_leg(m, wl, rate: float, mesh: int, t_steps: int, seconds_cap: float):
     return out
 
 
+# --- profile summaries (rocprofv3 output -> profiles/*.md) -------------------
+
+def _csv_rows(d: str, suffix: str):
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return rows
+
+
+def _bench_line(path: str) -> dict:
+    with open(path) as f:
+        lines = [ln for ln in f if ln.startswith("{")]
+    return json.loads(lines[-1])
+
+
+def _short(name: str) -> str:
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("mdeos::(anonymous namespace)::", "")
+    return n.split("(")[0] if not n.startswith("at::") else n.split("<")[0]
+
+
+def trace_summary(trace_dir: str, bench_json: str, cmd: str) -> str:
+    """Kernel-time summary of a `rocprofv3 --kernel-trace --stats` run of bench.py."""
+    b = _bench_line(bench_json)
+    stats = _csv_rows(trace_dir, "kernel_stats.csv")
+    trace = _csv_rows(trace_dir, "kernel_trace.csv")
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    top = stats[0]["Name"]
+    disp = sorted((r for r in trace if r["Kernel_Name"] == top), key=lambda r: int(r["Start_Timestamp"]))
+    timed = disp[-b["steps"]:]
+    avg = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in timed) / len(timed) / 1e6
+    kms = b["roofline"]["kernel_ms"]
+    out = [f"# {_short(top)} on {b['config']['workload']} ({b['config'].get('precision_mode', 'fp64')})", "",
+           "Command (from the repository root, on the GPU host):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp && cd -", cmd, "```", "",
+           "rocprofv3 kernel statistics (all dispatches of the run, warmup and its",
+           "launch-shape tuning chunks included):", "",
+           "| kernel | calls | average ms | total ms | % |", "|---|---|---|---|---|"]
+    for r in stats[:6]:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f} |")
+    out += ["", f"Timed dispatches of the dominant kernel (the last {len(timed)}): average "
+            f"**{avg:.3f} ms** per launch; bench.py's HIP-event time on the launch stream: "
+            f"**{kms:.3f} ms** (difference {100 * (avg - kms) / kms:+.2f} %).", "",
+            f"Full kernel name: `{top}`", "",
+            f"bench line: value {b['value']} {b['unit']}, roofline achieved {b['roofline']['achieved']} "
+            f"{b['roofline']['unit']} (frac {b['roofline']['frac']} of {b['roofline']['peak']}).", ""]
+    return "\n".join(out)
+
+
+def pmc_summary(fetch_dir: str, write_dir: str, bench_json: str, cmds: list[str]) -> str:
+    """HBM traffic of the dominant kernel from FETCH_SIZE and WRITE_SIZE passes,
+    each scaled by the same counter's reading for a plain device copy of
+    known size (the last dispatch of the run)."""
+    b = _bench_line(bench_json)
+    steps = b["steps"]
+    copy_bytes = b["copy_calibration"]["bytes"]
+    per = {}
+    for key, d, cname in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = [r for r in _csv_rows(d, "counter_collection.csv") if r["Counter_Name"] == cname]
+        by = {}
+        for r in rows:
+            by.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        ids = sorted(by)
+        adv = [by[i][1] for i in ids if f"::{ADVANCE}<" in by[i][0]][-steps:]
+        last = [by[i] for i in ids if "elementwise" in by[i][0]][-1]
+        per[key] = {"advance_kib": sum(adv) / len(adv), "copy_kib": last[1], "copy_kernel": _short(last[0])}
+    f_fetch = copy_bytes / (per["fetch"]["copy_kib"] * 1024.0)
+    f_write = copy_bytes / (per["write"]["copy_kib"] * 1024.0)
+    fetch_b = per["fetch"]["advance_kib"] * 1024.0 * f_fetch
+    write_b = per["write"]["advance_kib"] * 1024.0 * f_write
+    traffic = fetch_b + write_b
+    kms = b["roofline"]["kernel_ms"]
+    algo = b["roofline"].get("state_bytes_per_launch")
+    out = [f"# HBM traffic of {ADVANCE} on {b['config']['workload']} ({b['config'].get('precision_mode', 'fp64')})",
+           "", "Commands (from the repository root, on the GPU host):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp && cd -", *cmds, "```", "",
+           f"Calibration: the last dispatch of each run is a plain device copy (`{per['fetch']['copy_kernel']}`) "
+           f"of {copy_bytes} bytes read and written; factors known bytes / counter bytes: "
+           f"FETCH {f_fetch:.4f}, WRITE {f_write:.4f}.", "",
+           f"Per {ADVANCE} launch (mean of the {steps} timed dispatches):", "",
+           "| counter | KiB per launch | calibrated bytes | GB/s at the event-timed duration |",
+           "|---|---|---|---|",
+           f"| FETCH_SIZE | {per['fetch']['advance_kib']:.4g} | {fetch_b:.4g} | {fetch_b / kms / 1e6:.1f} |",
+           f"| WRITE_SIZE | {per['write']['advance_kib']:.4g} | {write_b:.4g} | {write_b / kms / 1e6:.1f} |",
+           "", f"Kernel duration (bench.py, HIP events): {kms:.3f} ms.",
+           f"Algorithmic bytes per launch (every atom's state read once and written once): {algo:.4g}." if algo else "",
+           "", "Read by bench.py (roofline.traffic) while the kernel sources are unchanged:", "",
+           f"- `traffic_bytes_per_launch`: {traffic:.6e}",
+           f"- `kernel_sources_sha256`: `{kernel_sources_sha256()}`", ""]
+    return "\n".join(out)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg5"], default="cfg2",
+                    help="cfg2: 4096 x 500 atoms (default); cfg3: 10,000 boxes of 108..4000 atoms; "
+                         "cfg5: 65,536 x 864 atoms at rc 4")
+    ap.add_argument("--precision", choices=["fp64", "kahan"], default="fp64",
+                    help="per-atom energy/virial accumulation")
+    ap.add_argument("--no-autotune", action="store_true", help="static launch-shape model only")
     ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=10000.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="end with one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
+                    help="write a markdown summary of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_LOG"),
+                    help="write a markdown summary of FETCH_SIZE / WRITE_SIZE runs and exit")
+    ap.add_argument("--cmd", action="append", default=[], help="command lines recorded in a summary")
+    ap.add_argument("--out", default=None, help="summary file (default: stdout)")
     args = ap.parse_args()
+
+    if args.trace_summary or args.pmc_summary:
+        text = (trace_summary(*args.trace_summary, " && ".join(args.cmd)) if args.trace_summary
+                else pmc_summary(*args.pmc_summary, args.cmd))
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(text)
+        else:
+            print(text)
+        return 0
+
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(boxes are independent, so several GPUs would each take a share of them); run with --gpus 1", file=sys.stderr)
+              "(boxes are independent, so several GPUs would each take a share of them); run with --gpus 1",
+              file=sys.stderr)
         return 2
 
     from paper_2508_06012_amd import mdeos as m
@@ -137,14 +304,18 @@ def main() -> int:
     try:
         import torch
         sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
-    except Exception:  # torch only provides the synchronisation bracket
+    except Exception:  # torch only provides the synchronisation bracket and the calibration copy
+        torch = None
         sync = lambda: None  # noqa: E731
 
-    w = wl.cfg2()
+    w = {"cfg2": wl.cfg2, "cfg3": wl.cfg3, "cfg5": wl.cfg5}[args.workload]()
+    default = args.workload == "cfg2"
+    prec = m.PREC_KAHAN if args.precision == "kahan" else m.PREC_FP64
     specs, sch = m.specs_from_workload(w)
     n = w.n
-    ctx = m.mdeos_create()
-    print(f"# workload {w.name}: {n} cells, {int(w.N[0])} atoms, {w.sched.n_steps} steps", file=sys.stderr, flush=True)
+    ctx = m.mdeos_create(autotune=0 if args.no_autotune else 1, precision=prec)
+    print(f"# workload {w.name}: {n} cells, {int(w.N.sum())} atoms, {w.sched.n_steps} steps, "
+          f"precision {args.precision}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         m.mdeos_eval_batch(ctx, specs, sch)
         print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
@@ -168,41 +339,64 @@ def main() -> int:
     flops = float(np.sum(res["pairs"] * (FLOP_PAIR * w.sched.n_steps + FLOP_PAIR_ENERGY * ne)))
     k_s = float(np.mean(kernel_ms)) / 1e3
     achieved = flops / k_s / 1e12
+    traffic = traffic_from_profile(args.workload, args.precision)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
             "peak_nonpacked": PEAK_FP32_NONPACKED, "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED, 4),
             "kernel_ms": round(float(np.mean(kernel_ms)), 3), "flops_per_launch": flops,
-            "flop_per_pair": FLOP_PAIR, "pairs_per_atom_step": float(np.mean(res["pairs"]) / w.N[0])}
-
-    # plain path on a stratified sample (same kernels, one cell per launch)
-    idx = np.linspace(0, n - 1, args.plain_sample).astype(int)
-    sub = (m.CellSpec * len(idx))(*[specs[int(i)] for i in idx])
-    t1 = time.perf_counter()
-    plain = m.mdeos_eval_plain(ctx, sub, sch)
-    t_plain = time.perf_counter() - t1
-    plain_evals = len(idx) / t_plain
-    bitwise = bool(plain.tobytes() == res[idx].tobytes())
-    dP = np.abs(plain["P"] - res[idx]["P"]) / np.maximum(np.hypot(plain["P_se"], res[idx]["P_se"]), 1e-300)
-    m.mdeos_destroy(ctx)
+            "flop_per_pair": FLOP_PAIR, "flop_per_pair_energy_step": FLOP_PAIR + FLOP_PAIR_ENERGY,
+            "pairs_per_atom_step": float(np.sum(res["pairs"]) / np.sum(w.N)),
+            "state_bytes_per_launch": float(2 * 72 * np.sum(w.N))}
+    if traffic is not None:
+        roof["traffic_GBps"] = round(traffic / k_s / 1e9, 1)
 
     out = {
         "metric": METRIC, "value": round(evals, 3), "unit": "EOS evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "cells": n, "atoms_per_cell": int(w.N[0]), "md_steps": w.sched.n_steps,
-                   "avg_window": w.sched.n_avg, "rc": 2.5, "dt": 0.004, "rho": [0.3, 1.1], "T": [0.8, 3.0],
-                   "precision": "fp32 pair forces; fp64 state, energy/virial reductions and re-pin"},
+        "config": {"workload": w.name, "cells": n, "atoms_per_cell": sorted(set(int(x) for x in w.N)),
+                   "md_steps": w.sched.n_steps, "avg_window": w.sched.n_avg,
+                   "rc": sorted(set(float(x) for x in w.rc)), "dt": float(w.dt[0]),
+                   "rho": [round(float(w.rho.min()), 3), round(float(w.rho.max()), 3)],
+                   "T": [round(float(w.T.min()), 3), round(float(w.T.max()), 3)],
+                   "precision_mode": args.precision, "autotune": not args.no_autotune,
+                   "precision": "fp32 pair forces; fp64 state, energy/virial sums, reductions and re-pin"
+                   if args.precision == "fp64" else
+                   "fp32 pair forces; Kahan fp32 per-atom energy/virial sums; fp64 state, reductions, re-pin"},
         "atom_steps_per_s": atom_steps,
         "failed_cells": failed,
-        "plain": {"sample": int(len(idx)), "evals_per_s": round(plain_evals, 3),
-                  "batched_over_plain": round(evals / plain_evals, 2), "bitwise_equal_to_batched": bitwise,
-                  "max_dP_over_combined_se": float(dP.max())},
         "roofline": roof,
     }
-    if not args.no_serve:
+    if default and not args.no_plain:
+        # plain path on a stratified sample (same kernels, one cell per launch)
+        idx = np.linspace(0, n - 1, args.plain_sample).astype(int)
+        sub = (m.CellSpec * len(idx))(*[specs[int(i)] for i in idx])
+        t1 = time.perf_counter()
+        plain = m.mdeos_eval_plain(ctx, sub, sch)
+        t_plain = time.perf_counter() - t1
+        plain_evals = len(idx) / t_plain
+        bitwise = bool(plain.tobytes() == res[idx].tobytes())
+        dP = np.abs(plain["P"] - res[idx]["P"]) / np.maximum(np.hypot(plain["P_se"], res[idx]["P_se"]), 1e-300)
+        out["plain"] = {"sample": int(len(idx)), "evals_per_s": round(plain_evals, 3),
+                        "batched_over_plain": round(evals / plain_evals, 2), "bitwise_equal_to_batched": bitwise,
+                        "max_dP_over_combined_se": float(dP.max())}
+        # single-cell latency: the 256-atom case, one cell per call
+        w1 = wl.cfg1()
+        s1, q1 = m.specs_from_workload(w1)
+        m.mdeos_eval_plain(ctx, s1, q1)
+        lat = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            r1 = m.mdeos_eval_plain(ctx, s1, q1)
+            lat.append(time.perf_counter() - t1)
+        out["cfg1"] = {"workload": w1.name, "wall_ms_per_eval": round(float(np.median(lat)) * 1e3, 3),
+                       "P": float(r1["P"][0]), "P_se": float(r1["P_se"][0]), "T": float(r1["T"][0]),
+                       "T_se": float(r1["T_se"][0])}
+    m.mdeos_destroy(ctx)
+    if default and not args.no_serve:
         print("# serving leg", file=sys.stderr, flush=True)
         out["serving"] = serve_leg(m, wl, args.serve_rate, mesh=32, t_steps=6, seconds_cap=30.0)
-    if not args.no_cpu:
+    if default and not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         cidx = np.linspace(0, n - 1, args.cpu_sample).astype(int)
         print(f"# cpu baseline: oracle on {len(cidx)} cells with {workers} processes", file=sys.stderr, flush=True)
@@ -212,6 +406,15 @@ def main() -> int:
                                "sample": f"{len(cidx)} stratified cells of {w.name}, full 2000-step schedule, "
                                          f"{cwall:.1f} s wall, one cell per process"}
         out["parity"] = {"cells": int(len(cidx)), "P_within_3_combined_se": int(wp), "T_within_3_combined_se": int(wt)}
+    if args.copy_mib > 0:
+        # a plain device copy of known size, last on the device (counter calibration)
+        nbytes = args.copy_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        bb = torch.empty_like(a)
+        sync()
+        torch.neg(a, out=bb)
+        sync()
+        out["copy_calibration"] = {"bytes": nbytes, "kernel": "torch.neg(float32)"}
     print(json.dumps(out), flush=True)
     return 0
 

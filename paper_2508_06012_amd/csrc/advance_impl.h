@@ -161,10 +161,15 @@ struct Box {
   CellRec* c;
   int N, G, n_pad, list_cap, ncell, nce, R;
   float L, rl, rl2, rc2, inv_ce;
+  float rlc2;  // (rl in cell edges)^2, widened by a relative 1e-4 so clipping stays conservative
   double invLw;
   double Lw, dt, hdt;
   double V, Ndof, u_shift;
   double Ecold;  // total cold energy (uniform across the workgroup)
+  // the schedule, read once per cell (the step loop writes other fields of
+  // the cell record, which would otherwise force these to be re-read)
+  int n_steps, n_avg, n_blocks, energy_every, debug_energy, n_rescale;
+  int rescale_at[MDEOS_MAX_RESCALE];
   bool kahan;    // per-atom energy/virial sums in compensated FP32 (uniform)
 
   // owned atoms: a = t + k BLOCK
@@ -217,6 +222,10 @@ struct Box {
     R = c->stencil;
     ncell = nce * nce * nce;
     inv_ce = MI ? (float)nce / L : (float)nce / (L + 2.0f * rl);
+    {
+      const float rlc = rl * inv_ce * 1.0001f;
+      rlc2 = rlc * rlc;
+    }
     invLw = 1.0 / c->Lw;
     V = c->V;
     Ndof = 3.0 * N - 3.0;
@@ -224,6 +233,14 @@ struct Box {
     double irc6 = irc2 * irc2 * irc2;
     u_shift = 4.0 * (irc6 * irc6 - irc6);
     Ecold = c->Ecold;
+    n_steps = c->n_steps;
+    n_avg = c->n_avg;
+    n_blocks = c->n_blocks;
+    energy_every = c->energy_every;
+    debug_energy = c->debug_energy;
+    n_rescale = c->n_rescale;
+#pragma unroll
+    for (int r = 0; r < MDEOS_MAX_RESCALE; ++r) rescale_at[r] = r < n_rescale ? c->rescale_steps[r] : -1;
   }
 
   // --- block helpers --------------------------------------------------------
@@ -427,52 +444,97 @@ struct Box {
     for (int k = 0; k < APT; ++k) {
       int a = t + k * BLOCK;
       int cnt = 0;
+      auto push = [&](uint32_t v) __attribute__((always_inline)) {
+        if (cnt < list_cap) list[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)v;
+        ++cnt;
+      };
+      // Appends the atoms sorted[lo..hi) within rl of the build position of
+      // atom a, in order. Four candidates per round: their indices and
+      // positions are all loaded before the first is tested, so the LDS
+      // latency of the dependent loads is paid once per four. Slots past hi
+      // point at the atom itself, which the e != a test drops.
+      const float bxi = bx[k], byi = by[k], bzi = bz[k];
+      auto scan = [&](int lo, int hi) __attribute__((always_inline)) {
+        for (int q = lo; q < hi; q += 4) {
+          int e4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = sorted[min(q + u, hi - 1)];
+            e4[u] = q + u < hi ? e : a;
+          }
+          float d2[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float ddx, ddy, ddz;
+            if (MI) {
+              ddx = (float)mimg((double)bxi - (double)PX(e4[u]));
+              ddy = (float)mimg((double)byi - (double)PY(e4[u]));
+              ddz = (float)mimg((double)bzi - (double)PZ(e4[u]));
+            } else {
+              ddx = bxi - PX(e4[u]);
+              ddy = byi - PY(e4[u]);
+              ddz = bzi - PZ(e4[u]);
+            }
+            d2[u] = ddx * ddx + ddy * ddy + ddz * ddz;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (d2[u] < rl2 && e4[u] != a) push((uint32_t)(PB * e4[u]));
+        }
+      };
       if (a < N && MI) {
-        // periodic stencil, one cell at a time (the grid has at least 2R+1 cells per edge)
+        // periodic stencil, one cell at a time (the grid has at least 2R+1
+        // cells per edge); rows and cells the rl-sphere cannot reach are
+        // skipped (see the ghost branch)
         const float xi = bx[k], yi = by[k], zi = bz[k];
         const int cx = cell_coord(xi), cy = cell_coord(yi), cz = cell_coord(zi);
+        const float ux = xi * inv_ce, uy = yi * inv_ce, uz = zi * inv_ce;
         for (int dz = -R; dz <= R; ++dz) {
+          const float gz = fmaxf(0.f, fmaxf((float)(cz + dz) - uz, uz - (float)(cz + dz + 1)));
+          const float rz = rlc2 - gz * gz;
+          if (rz <= 0.f) continue;
           const int zz = wrapc(cz + dz);
           for (int dy = -R; dy <= R; ++dy) {
+            const float gy = fmaxf(0.f, fmaxf((float)(cy + dy) - uy, uy - (float)(cy + dy + 1)));
+            const float rr = rz - gy * gy;
+            if (rr <= 0.f) continue;
+            const float wx = sqrtf(rr);
             const int yy = wrapc(cy + dy);
-            for (int dx = -R; dx <= R; ++dx) {
+            const int x0 = max(cx - R, (int)floorf(ux - wx)), x1 = min(cx + R, (int)floorf(ux + wx));
+            for (int dx = x0 - cx; dx <= x1 - cx; ++dx) {
               const int cq = (zz * nce + yy) * nce + wrapc(cx + dx);
-              const int lo = cstart[cq], hi = cstart[cq + 1];
-              for (int q = lo; q < hi; ++q) {
-                const int e = sorted[q];
-                const float ddx = (float)mimg((double)xi - (double)PX(e));
-                const float ddy = (float)mimg((double)yi - (double)PY(e));
-                const float ddz = (float)mimg((double)zi - (double)PZ(e));
-                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                if (r2 < rl2 && e != a) {
-                  if (cnt < list_cap) list[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)(PB * e);
-                  ++cnt;
-                }
-              }
+              scan(cstart[cq], cstart[cq + 1]);
             }
           }
         }
       } else if (a < N) {
+        // Rows (dy, dz) of the stencil in fixed order. In cell units (u = the
+        // atom's fractional cell coordinate) a row is skipped when its y and z
+        // cell intervals are at least rl away, and its x range is cut to the
+        // cells that the chord of the rl-sphere touches: only cells holding no
+        // point within rl are dropped, so the list and its order are those of
+        // the full stencil.
         const float xi = bx[k], yi = by[k], zi = bz[k];
         const int cx = cell_coord(xi), cy = cell_coord(yi), cz = cell_coord(zi);
-        const int x0 = max(cx - R, 0), x1 = min(cx + R, nce - 1);
+        const float ux = (xi + rl) * inv_ce, uy = (yi + rl) * inv_ce, uz = (zi + rl) * inv_ce;
         for (int dz = -R; dz <= R; ++dz) {
           const int zz = cz + dz;
           if (zz < 0 || zz >= nce) continue;
+          const float gz = fmaxf(0.f, fmaxf((float)zz - uz, uz - (float)(zz + 1)));
+          const float rz = rlc2 - gz * gz;
+          if (rz <= 0.f) continue;
           for (int dy = -R; dy <= R; ++dy) {
             const int yy = cy + dy;
             if (yy < 0 || yy >= nce) continue;
+            const float gy = fmaxf(0.f, fmaxf((float)yy - uy, uy - (float)(yy + 1)));
+            const float rr = rz - gy * gy;
+            if (rr <= 0.f) continue;
+            const float wx = sqrtf(rr);
+            const int x0 = max(max(cx - R, 0), (int)floorf(ux - wx));
+            const int x1 = min(min(cx + R, nce - 1), (int)floorf(ux + wx));
+            if (x0 > x1) continue;
             const int row = (zz * nce + yy) * nce;
-            const int lo = cstart[row + x0], hi = cstart[row + x1 + 1];
-            for (int q = lo; q < hi; ++q) {
-              const int e = sorted[q];
-              const float ddx = xi - PX(e), ddy = yi - PY(e), ddz = zi - PZ(e);
-              const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-              if (r2 < rl2 && e != a) {
-                if (cnt < list_cap) list[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)(4 * e);
-                ++cnt;
-              }
-            }
+            scan(cstart[row + x0], cstart[row + x1 + 1]);
           }
         }
       }
@@ -488,7 +550,11 @@ struct Box {
       if (a < n_pad) {
         int from = (a < N) ? min(cnt, list_cap) : 0;
         const uint16_t pad = (uint16_t)(PB * (MI ? (a < N ? a : SENT) : SENT));
-        for (int q = from; q < 8 * nb; ++q) list[(((q >> 3) * n_pad + a) << 3) + (q & 7)] = pad;
+        // the open row entry by entry, then whole 16-byte padding rows
+        int q = from;
+        for (; (q & 7) && q < 8 * nb; ++q) list[(((q >> 3) * n_pad + a) << 3) + (q & 7)] = pad;
+        const uint32_t pp = (uint32_t)pad * 0x00010001u;
+        for (int b = q >> 3; b < nb; ++b) reinterpret_cast<uint4*>(list)[b * n_pad + a] = make_uint4(pp, pp, pp, pp);
       }
     }
     if (over) ctl->overflow = 1;
@@ -646,21 +712,27 @@ struct Box {
   // --- per-step bookkeeping (FP64) --------------------------------------------------
 
   DEVI bool is_rescale(int k) const {
-    for (int r = 0; r < c->n_rescale; ++r)
-      if (c->rescale_steps[r] == k) return true;
+    bool hit = false;
+#pragma unroll
+    for (int r = 0; r < MDEOS_MAX_RESCALE; ++r) hit = hit || rescale_at[r] == k;
+    return hit;
     return false;
   }
   DEVI bool is_energy_step(int k) const {
-    const int n = c->n_steps, w0 = n - c->n_avg;
-    return c->debug_energy || (k % c->energy_every == 0) || k == n || k == w0 || is_rescale(k);
+    const int n = n_steps, w0 = n - n_avg;
+    return debug_energy || (k % energy_every == 0) || k == n || k == w0 || is_rescale(k);
   }
 
   // Observables of step k from the block sums (wave 0 only; all lanes compute
   // the same values, lane 0 writes). Eq. stress: P = (2K + W) / (3V).
+  DEVI double pressure(double K, double W) const { return (2.0 * K + W) / (3.0 * V); }
+  DEVI double temperature(double K) const { return 2.0 * K / Ndof; }
   DEVI void observe(int k, double K, double W, double U, bool energy) {
-    const int n = c->n_steps, w0 = n - c->n_avg;
-    const double P = (2.0 * K + W) / (3.0 * V);
-    const double T = 2.0 * K / Ndof;
+    record(k, K, W, U, pressure(K, W), temperature(K), energy);
+  }
+  // Folds step k (P and T already formed) into the accumulators, in step order.
+  DEVI void record(int k, double K, double W, double U, double P, double T, bool energy) {
+    const int n = n_steps, w0 = n - n_avg;
     bool bad = !isfinite(K) || !isfinite(W) || (energy && !isfinite(U));
     if (lane == 0) {
       if (bad) {
@@ -672,14 +744,14 @@ struct Box {
       if (energy) ctl->U = U;
       if (k > w0) {
         const int idx = k - w0 - 1;
-        const int bl = c->n_avg / c->n_blocks;
+        const int bl = n_avg / n_blocks;
         const int b = idx / bl;
         ctl->sumP[b] += P;
         ctl->sumT[b] += T;
         if (idx == 0) ctl->P_ref = P;
         const double dp = P - ctl->P_ref;
         ctl->sumdP2 += dp * dp;
-        if (energy && (k % c->energy_every == 0 || k == n)) {
+        if (energy && (k % energy_every == 0 || k == n)) {
           ctl->sumU += U;
           ctl->nU += 1;
         }
@@ -690,11 +762,13 @@ struct Box {
   }
 
   // Steps k_first..k_last have their group sums in ring slots (k % ring).
+  // Lane s forms step k_first + s (box sums, P, T); the accumulation then
+  // runs in step order.
   DEVI void flush(int k_first, int k_last) {
     if (wv != 0 || k_last < k_first) return;
     const int R = p.caps.ring;
     const int cnt = k_last - k_first + 1;
-    double Ks = 0.0, Ws = 0.0, Us = 0.0;
+    double Ks = 0.0, Ws = 0.0, Us = 0.0, Ps = 0.0, Ts = 0.0;
     if (lane < cnt) {
       const double* r = ring + (size_t)((k_first + lane) % R) * 3 * p.caps.gmax;
       for (int g = 0; g < G; ++g) {
@@ -702,11 +776,14 @@ struct Box {
         Ws += r[3 * g + 1];
         Us += r[3 * g + 2];
       }
+      Ps = pressure(Ks, Ws);
+      Ts = temperature(Ks);
     }
     for (int s = 0; s < cnt; ++s) {
       const double K = readlane_d(Ks, s), W = readlane_d(Ws, s), U = readlane_d(Us, s);
+      const double P = readlane_d(Ps, s), T = readlane_d(Ts, s);
       const int k = k_first + s;
-      observe(k, K, W, U, is_energy_step(k));
+      record(k, K, W, U, P, T, is_energy_step(k));
     }
   }
 
@@ -1005,7 +1082,7 @@ struct Box {
   }
 
   DEVI void advance_steps(int step) {
-    const int n = c->n_steps;
+    const int n = n_steps;
     int target = n;
     if (p.step_budget > 0) target = min(n, step + p.step_budget);
     else if (p.step_budget < 0) target = step;
@@ -1059,7 +1136,7 @@ struct Box {
 #pragma unroll
         for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
         ++esteps;
-      } else if (k > c->n_steps - c->n_avg || c->debug_energy) {
+      } else if (k > n_steps - n_avg || debug_energy) {
         forces<ACC_FW>();  // the virial enters P only inside the averaging window
       } else {
         forces<ACC_F>();

@@ -60,6 +60,8 @@ class _Sched(C.Structure):
         ("energy_every", C.c_int),
         ("drift_tol", C.c_double),
         ("eps", C.c_double),
+        ("ensemble", C.c_int),
+        ("gamma", C.c_double),
     ]
 
 
@@ -89,6 +91,7 @@ def lib():
         _lib.orc_philox4x64_10.argtypes = [C.POINTER(C.c_uint64)] * 3
         _lib.orc_gauss.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int]
         _lib.orc_gauss.restype = C.c_double
+        _lib.orc_noise3.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, dp]
         _lib.orc_lattice_param.argtypes = [C.c_double]
         _lib.orc_lattice_param.restype = C.c_double
         _lib.orc_box_length.argtypes = [C.c_int, C.c_double]
@@ -145,6 +148,8 @@ class Schedule:
     energy_every: int = 10
     drift_tol: float = 0.05
     eps: float = 1.0
+    ensemble: int = 0  # 0: velocity Verlet + energy re-pins; 1: GJF Langevin + temperature updates
+    gamma: float = 0.0  # Langevin friction (ensemble 1)
 
     def _c(self) -> _Sched:
         s = _Sched()
@@ -153,6 +158,7 @@ class Schedule:
         for i, k in enumerate(self.rescale_steps):
             s.rescale_steps[i] = k
         s.energy_every, s.drift_tol, s.eps = self.energy_every, self.drift_tol, self.eps
+        s.ensemble, s.gamma = self.ensemble, self.gamma
         return s
 
 
@@ -197,6 +203,13 @@ def philox4x64_10(key, ctr) -> np.ndarray:
 
 def gauss(seed: int, cell_id: int, atom: int, comp: int) -> float:
     return lib().orc_gauss(seed & (2**64 - 1), cell_id, atom, comp)
+
+
+def noise3(seed: int, cell_id: int, atom: int, step: int) -> np.ndarray:
+    """Thermostat noise of one atom at one step: three standard normals."""
+    z = np.zeros(3)
+    lib().orc_noise3(seed & (2**64 - 1), cell_id, atom, step, z.ctypes.data_as(C.POINTER(C.c_double)))
+    return z
 
 
 def lattice_param(rho: float) -> float:

@@ -15,7 +15,10 @@
  *     lattice, first-guess temperature, Gaussian velocities, temperature
  *     update of Eq. Tcontribution;
  *   - microscopic model (Sec. II.B): Newton's equations integrated with
- *     velocity Verlet, periodic boundaries;
+ *     velocity Verlet, periodic boundaries; or, for thermostatted lifting and
+ *     canonical (NVT) production (Sec. III), the GJF Langevin integrator the
+ *     paper cites (Sec. II.B) with the iterated temperature updates of
+ *     Eq. Tcontribution;
  *   - restricting operator (Sec. III, Eq. stress): pressure as one third of
  *     the trace of the kinetic + virial stress, time averaged; fluctuation
  *     reported as an RMS (Sec. IV.B).
@@ -54,6 +57,8 @@ typedef struct {
     int energy_every;     /* potential energy enters <E_pot> on steps divisible by this */
     double drift_tol;     /* |E(n) - E(n - n_avg)| / N above this sets the drift status */
     double eps;           /* LJ well depth (1 in reduced units; 0 switches the potential off) */
+    int ensemble;         /* 0: velocity Verlet with energy re-pins; 1: Langevin (GJF) with temperature updates */
+    double gamma;         /* Langevin friction (ensemble 1) */
 } orc_sched;
 
 typedef struct {
@@ -118,6 +123,30 @@ double orc_gauss(uint64_t seed, int64_t cell_id, int64_t a, int c)
  * parameter l = (alpha / rho)^(1/3), box edge L = n_c l, N = alpha n_c^3.
  * Atom a = 4((ix n_c + iy) n_c + iz) + b sits at l((ix,iy,iz) + basis_b + 1/4).
  * ------------------------------------------------------------------------- */
+/* Thermostat noise of atom a at step k: three standard normal numbers from one
+ * Philox4x64-10 block with key (seed, cell_id) and counter (a, k, 1, 0)
+ * (the third counter word keeps this stream apart from the lift's draws).
+ * Box-Muller on words (0, 1) gives z0 = R cos(theta), z1 = R sin(theta); on
+ * words (2, 3), z2 = R' cos(theta'), with u = 1 - (w >> 11) 2^-53 for the
+ * radius and u = (w >> 11) 2^-53 for the angle. */
+void orc_noise3(uint64_t seed, int64_t cell_id, int64_t a, int64_t k, double z[3])
+{
+    const double two_m53 = 1.0 / 9007199254740992.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t key[2] = {seed, (uint64_t)cell_id};
+    uint64_t ctr[4] = {(uint64_t)a, (uint64_t)k, 1u, 0u};
+    uint64_t w[4];
+    orc_philox4x64_10(key, ctr, w);
+    double u1 = 1.0 - (double)(w[0] >> 11) * two_m53;
+    double u2 = (double)(w[1] >> 11) * two_m53;
+    double u3 = 1.0 - (double)(w[2] >> 11) * two_m53;
+    double u4 = (double)(w[3] >> 11) * two_m53;
+    double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    z[0] = r1 * cos(two_pi * u2);
+    z[1] = r1 * sin(two_pi * u2);
+    z[2] = r2 * cos(two_pi * u4);
+}
+
 double orc_lattice_param(double rho) { return cbrt(4.0 / rho); }
 double orc_box_length(int n_c, double rho) { return n_c * orc_lattice_param(rho); }
 
@@ -343,6 +372,15 @@ static int in_schedule(const orc_sched *s, int k)
     return 0;
 }
 
+/* First scheduled step >= k, or -1. */
+static int next_update(const orc_sched *s, int k)
+{
+    int best = -1;
+    for (int r = 0; r < s->n_rescale; ++r)
+        if (s->rescale_steps[r] >= k && (best < 0 || s->rescale_steps[r] < best)) best = s->rescale_steps[r];
+    return best;
+}
+
 /* ---------------------------------------------------------------------------
  * Advance and restrict.
  * Microscopic model (Sec. II.B): velocity Verlet, positions wrapped into
@@ -357,6 +395,21 @@ static int in_schedule(const orc_sched *s, int k)
  * contiguous blocks; P_rms is the RMS deviation of the instantaneous P from
  * its mean (the fluctuation measure of Sec. IV).
  * Observables of a rescale step are taken after the rescale.
+ *
+ * Thermostatted lifting and canonical production (ensemble 1; Sec. III with
+ * the GJF integrator of Sec. II.B, unit mass, k_B = 1). One step is
+ *   x' = x + b dt v + (b dt^2 / 2) f + (b dt / 2) beta
+ *   v' = a v + (dt / 2) (a f + f') + b beta
+ * with c = gamma dt / 2, b = 1 / (1 + c), a = (1 - c) / (1 + c) and beta a
+ * Gaussian vector of variance 2 gamma T_th dt per component (orc_noise3 for
+ * the step). T_th starts at the first guess 2 N e / N_DOF (all energy
+ * kinetic). At each scheduled step s the temperature update of
+ * Eq. Tcontribution uses the potential energy sampled over the second half of
+ * the segment since the previous update (steps k > mid, mid = prev +
+ * (s - prev) / 2, taken at steps divisible by energy_every and at s itself;
+ * the instantaneous value if there is none): T = 2 (N e - (<E_pot> - E_cold))
+ * / N_DOF; velocities are scaled to that temperature and it becomes T_th.
+ * The energy-drift status does not apply (energy is not conserved).
  *
  * State (x, v) is advanced in place. Records: K, U, W, P, T for steps
  * 0..n_steps (arrays of n_steps + 1, may be NULL) and forces for steps
@@ -384,11 +437,18 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
     double sumU = 0.0;
     int nU = 0;
     double E_w0 = 0.0, E_n = 0.0;
+    int nvt = sch->ensemble == 1;
+    double T_th = 2.0 * N * cell->e / Ndof;
+    double gc = 0.5 * sch->gamma * dt, gb = 1.0 / (1.0 + gc), ga = (1.0 - gc) / (1.0 + gc);
+    double *beta = (double *)malloc(sizeof(double) * 3 * N);
+    double *Fold = (double *)malloc(sizeof(double) * 3 * N);
+    int prev = 0, segN = 0;
+    double segU = 0.0;
 
     orc_forces(N, L, cell->rc, sch->eps, x, F, &U, &W);
     K = kinetic(N, v);
     for (int k = 0; k <= n; ++k) {
-        if (k > 0) {
+        if (k > 0 && !nvt) {
             for (int i = 0; i < 3 * N; ++i) {
                 v[i] += 0.5 * dt * F[i];
                 x[i] += dt * v[i];
@@ -398,12 +458,35 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
             orc_forces(N, L, cell->rc, sch->eps, x, F, &U, &W);
             for (int i = 0; i < 3 * N; ++i) v[i] += 0.5 * dt * F[i];
             K = kinetic(N, v);
+        } else if (k > 0) {
+            double sig = sqrt(2.0 * sch->gamma * T_th * dt);
+            for (int a = 0; a < N; ++a) {
+                double z[3];
+                orc_noise3(cell->seed, cell->cell_id, a, k, z);
+                for (int c = 0; c < 3; ++c) beta[3 * a + c] = sig * z[c];
+            }
+            for (int i = 0; i < 3 * N; ++i) {
+                x[i] += gb * dt * v[i] + 0.5 * gb * dt * dt * F[i] + 0.5 * gb * dt * beta[i];
+                x[i] -= L * floor(x[i] / L);
+                if (x[i] >= L) x[i] = 0.0;
+                Fold[i] = F[i];
+            }
+            orc_forces(N, L, cell->rc, sch->eps, x, F, &U, &W);
+            for (int i = 0; i < 3 * N; ++i) v[i] = ga * v[i] + 0.5 * dt * (ga * Fold[i] + F[i]) + gb * beta[i];
+            K = kinetic(N, v);
         }
         if (!isfinite(K) || !isfinite(U) || !isfinite(W)) {
             status |= ORC_NONFINITE;
             break;
         }
-        if (in_schedule(sch, k)) {
+        if (nvt) {
+            int s = next_update(sch, k);
+            if (s >= 0 && k > prev + (s - prev) / 2 && (k % sch->energy_every == 0 || k == s)) {
+                segU += U;
+                segN += 1;
+            }
+        }
+        if (in_schedule(sch, k) && !nvt) {
             double Kt = N * cell->e - (U - Ecold_total);
             if (Kt <= 0.0) {
                 status |= ORC_BELOW_COLD;
@@ -412,6 +495,20 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
                 for (int i = 0; i < 3 * N; ++i) v[i] *= lam;
                 K = kinetic(N, v);
             }
+        } else if (in_schedule(sch, k)) {
+            double Ubar = segN > 0 ? segU / segN : U;
+            double Tn = 2.0 * (N * cell->e - (Ubar - Ecold_total)) / Ndof;
+            if (Tn <= 0.0) {
+                status |= ORC_BELOW_COLD;
+            } else {
+                double lam = sqrt(Tn / (2.0 * K / Ndof));
+                for (int i = 0; i < 3 * N; ++i) v[i] *= lam;
+                K = kinetic(N, v);
+                T_th = Tn;
+            }
+            prev = k;
+            segU = 0.0;
+            segN = 0;
         }
         double P = (2.0 * K + W) / (3.0 * V);
         double T = 2.0 * K / Ndof;
@@ -446,11 +543,13 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
         res->P_rms = sqrt(acc / sch->n_avg);
         res->Epot_mean = nU > 0 ? sumU / nU / N : NAN;
         res->drift = (E_n - E_w0) / N;
-        if (fabs(res->drift) > sch->drift_tol) status |= ORC_DRIFT;
+        if (!nvt && fabs(res->drift) > sch->drift_tol) status |= ORC_DRIFT;
         res->n_samples = sch->n_avg;
     }
     res->status = status;
     free(F);
     free(Pser);
     free(Tser);
+    free(beta);
+    free(Fold);
 }

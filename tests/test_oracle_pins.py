@@ -359,3 +359,48 @@ def test_block_se_matches_ar1_analytic():
     assert np.mean(se2) == pytest.approx(analytic2, rel=tol)
     # and the observed spread of the means agrees too
     assert np.var(means, ddof=1) == pytest.approx(analytic2, rel=3.5 * math.sqrt(2 / reps))
+
+
+# --- thermostatted lifting and canonical production (GJF Langevin) -----------
+
+def test_thermostat_noise_definition():
+    # one Philox block at counter (atom, step, 1, 0), numpy's generator for the
+    # words, Box-Muller written out here: (cos, sin) of words 0-1, cos of 2-3
+    key, a, k = (11, 4), 17, 9
+    c = [a - 1, k, 1, 0]  # numpy pre-increments the counter
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    w = [int(bg.random_raw()) for _ in range(4)]
+    u = [1.0 - (w[0] >> 11) * 2.0 ** -53, (w[1] >> 11) * 2.0 ** -53,
+         1.0 - (w[2] >> 11) * 2.0 ** -53, (w[3] >> 11) * 2.0 ** -53]
+    r1, r2 = math.sqrt(-2 * math.log(u[0])), math.sqrt(-2 * math.log(u[2]))
+    want = [r1 * math.cos(2 * math.pi * u[1]), r1 * math.sin(2 * math.pi * u[1]), r2 * math.cos(2 * math.pi * u[3])]
+    assert oracle.noise3(*key, a, k) == pytest.approx(want, rel=1e-14, abs=1e-15)
+    z = np.array([oracle.noise3(5, 2, a, k) for a in range(300) for k in range(1, 8)]).ravel()
+    assert abs(z.mean()) < 4 / math.sqrt(z.size) and abs(z.var() - 1) < 4 * math.sqrt(2 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+
+
+def test_gjf_without_friction_is_velocity_verlet():
+    """gamma = 0 makes a = b = 1 and the noise zero: the GJF step is then the
+    velocity-Verlet step (rearranged, so equal up to rounding)."""
+    cell = oracle.Cell(rho=0.8, e=1.5, n_c=3, rc=2.5, dt=0.005, seed=3, cell_id=1)
+    x0, v0, Ec = oracle.lift(cell)
+    a = oracle.run(cell, oracle.Schedule(200, 100, n_blocks=10), x=x0, v=v0, Ecold_total=Ec)
+    b = oracle.run(cell, oracle.Schedule(200, 100, n_blocks=10, ensemble=1, gamma=0.0), x=x0, v=v0, Ecold_total=Ec)
+    assert np.abs(a.x - b.x).max() < 1e-9 and np.abs(a.v - b.v).max() < 1e-9
+    assert np.abs(a.U - b.U).max() < 1e-9 * abs(a.U).max()
+
+
+@pytest.mark.parametrize("gamma,dt", [(5.0, 0.02), (0.5, 0.005)])
+def test_gjf_free_particles_sample_the_exact_temperature(gamma, dt):
+    """With the potential off, GJF's on-site velocities have stationary
+    variance exactly T per component for any dt: v' = a v + b beta gives
+    <v^2> = b^2 2 gamma T dt / (1 - a^2) = T. A wrong damping or noise factor
+    shows up at order gamma dt (10 % for the first case)."""
+    N = 256
+    T = 1.7
+    cell = oracle.Cell(rho=0.5, e=1.5 * T * (1 - 1 / N), n_c=4, rc=2.5, dt=dt, seed=21, cell_id=5)
+    r = oracle.run(cell, oracle.Schedule(6000, 5000, n_blocks=20, ensemble=1, gamma=gamma, eps=0.0))
+    t = 2 * r.K[1001:] / (3 * N)  # per-component variance of the velocities
+    m, se = oracle.block_stats(t, 20)
+    assert abs(m - T) <= 4 * se and abs(m - T) <= 0.02 * T, (m, se)

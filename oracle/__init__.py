@@ -47,6 +47,7 @@ class _Cell(C.Structure):
         ("dt", C.c_double),
         ("seed", C.c_uint64),
         ("cell_id", C.c_int64),
+        ("query", C.c_int64),
     ]
 
 
@@ -91,7 +92,7 @@ def lib():
         _lib.orc_philox4x64_10.argtypes = [C.POINTER(C.c_uint64)] * 3
         _lib.orc_gauss.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int]
         _lib.orc_gauss.restype = C.c_double
-        _lib.orc_noise3.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, dp]
+        _lib.orc_noise3.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, C.c_int64, dp]
         _lib.orc_lattice_param.argtypes = [C.c_double]
         _lib.orc_lattice_param.restype = C.c_double
         _lib.orc_box_length.argtypes = [C.c_int, C.c_double]
@@ -130,13 +131,14 @@ class Cell:
     dt: float = 0.005
     seed: int = 20250806
     cell_id: int = 0
+    query: int = 0  # index of this query of the cell (thermostat noise counter word 3)
 
     @property
     def N(self) -> int:
         return 4 * self.n_c ** 3
 
     def _c(self) -> _Cell:
-        return _Cell(self.rho, self.e, self.n_c, self.rc, self.dt, self.seed & (2**64 - 1), self.cell_id)
+        return _Cell(self.rho, self.e, self.n_c, self.rc, self.dt, self.seed & (2**64 - 1), self.cell_id, self.query)
 
 
 @dataclass
@@ -205,10 +207,10 @@ def gauss(seed: int, cell_id: int, atom: int, comp: int) -> float:
     return lib().orc_gauss(seed & (2**64 - 1), cell_id, atom, comp)
 
 
-def noise3(seed: int, cell_id: int, atom: int, step: int) -> np.ndarray:
-    """Thermostat noise of one atom at one step: three standard normals."""
+def noise3(seed: int, cell_id: int, atom: int, step: int, query: int = 0) -> np.ndarray:
+    """Thermostat noise of one atom at one step of a query: three standard normals."""
     z = np.zeros(3)
-    lib().orc_noise3(seed & (2**64 - 1), cell_id, atom, step, z.ctypes.data_as(C.POINTER(C.c_double)))
+    lib().orc_noise3(seed & (2**64 - 1), cell_id, atom, step, query, z.ctypes.data_as(C.POINTER(C.c_double)))
     return z
 
 

@@ -46,6 +46,7 @@ typedef struct {
     double dt;       /* time step */
     uint64_t seed;   /* Philox key word 0 */
     int64_t cell_id; /* Philox key word 1 */
+    int64_t query;   /* index of this query of the cell (0 for the first); thermostat counter word 3 */
 } orc_cell;
 
 typedef struct {
@@ -123,18 +124,19 @@ double orc_gauss(uint64_t seed, int64_t cell_id, int64_t a, int c)
  * parameter l = (alpha / rho)^(1/3), box edge L = n_c l, N = alpha n_c^3.
  * Atom a = 4((ix n_c + iy) n_c + iz) + b sits at l((ix,iy,iz) + basis_b + 1/4).
  * ------------------------------------------------------------------------- */
-/* Thermostat noise of atom a at step k: three standard normal numbers from one
- * Philox4x64-10 block with key (seed, cell_id) and counter (a, k, 1, 0)
- * (the third counter word keeps this stream apart from the lift's draws).
+/* Thermostat noise of atom a at step k of query q: three standard normal
+ * numbers from one Philox4x64-10 block with key (seed, cell_id) and counter
+ * (a, k, 1, q) (the third counter word keeps this stream apart from the
+ * lift's draws, the fourth apart from the cell's earlier queries).
  * Box-Muller on words (0, 1) gives z0 = R cos(theta), z1 = R sin(theta); on
  * words (2, 3), z2 = R' cos(theta'), with u = 1 - (w >> 11) 2^-53 for the
  * radius and u = (w >> 11) 2^-53 for the angle. */
-void orc_noise3(uint64_t seed, int64_t cell_id, int64_t a, int64_t k, double z[3])
+void orc_noise3(uint64_t seed, int64_t cell_id, int64_t a, int64_t k, int64_t q, double z[3])
 {
     const double two_m53 = 1.0 / 9007199254740992.0;
     const double two_pi = 6.283185307179586476925286766559;
     uint64_t key[2] = {seed, (uint64_t)cell_id};
-    uint64_t ctr[4] = {(uint64_t)a, (uint64_t)k, 1u, 0u};
+    uint64_t ctr[4] = {(uint64_t)a, (uint64_t)k, 1u, (uint64_t)q};
     uint64_t w[4];
     orc_philox4x64_10(key, ctr, w);
     double u1 = 1.0 - (double)(w[0] >> 11) * two_m53;
@@ -462,7 +464,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
             double sig = sqrt(2.0 * sch->gamma * T_th * dt);
             for (int a = 0; a < N; ++a) {
                 double z[3];
-                orc_noise3(cell->seed, cell->cell_id, a, k, z);
+                orc_noise3(cell->seed, cell->cell_id, a, k, cell->query, z);
                 for (int c = 0; c < 3; ++c) beta[3 * a + c] = sig * z[c];
             }
             for (int i = 0; i < 3 * N; ++i) {

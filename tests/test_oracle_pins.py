@@ -364,17 +364,19 @@ def test_block_se_matches_ar1_analytic():
 # --- thermostatted lifting and canonical production (GJF Langevin) -----------
 
 def test_thermostat_noise_definition():
-    # one Philox block at counter (atom, step, 1, 0), numpy's generator for the
-    # words, Box-Muller written out here: (cos, sin) of words 0-1, cos of 2-3
-    key, a, k = (11, 4), 17, 9
-    c = [a - 1, k, 1, 0]  # numpy pre-increments the counter
+    # one Philox block at counter (atom, step, 1, query), numpy's generator
+    # for the words, Box-Muller written out here: (cos, sin) of words 0-1,
+    # cos of 2-3
+    key, a, k, q = (11, 4), 17, 9, 3
+    c = [a - 1, k, 1, q]  # numpy pre-increments the counter
     bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
     w = [int(bg.random_raw()) for _ in range(4)]
     u = [1.0 - (w[0] >> 11) * 2.0 ** -53, (w[1] >> 11) * 2.0 ** -53,
          1.0 - (w[2] >> 11) * 2.0 ** -53, (w[3] >> 11) * 2.0 ** -53]
     r1, r2 = math.sqrt(-2 * math.log(u[0])), math.sqrt(-2 * math.log(u[2]))
     want = [r1 * math.cos(2 * math.pi * u[1]), r1 * math.sin(2 * math.pi * u[1]), r2 * math.cos(2 * math.pi * u[3])]
-    assert oracle.noise3(*key, a, k) == pytest.approx(want, rel=1e-14, abs=1e-15)
+    assert oracle.noise3(*key, a, k, q) == pytest.approx(want, rel=1e-14, abs=1e-15)
+    assert np.abs(oracle.noise3(*key, a, k, 0) - oracle.noise3(*key, a, k, q)).max() > 0.01
     z = np.array([oracle.noise3(5, 2, a, k) for a in range(300) for k in range(1, 8)]).ravel()
     assert abs(z.mean()) < 4 / math.sqrt(z.size) and abs(z.var() - 1) < 4 * math.sqrt(2 / z.size)
     assert stats.kstest(z, "norm").pvalue > 1e-3

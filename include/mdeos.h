@@ -76,7 +76,24 @@ typedef struct {
     int rescale_steps[MDEOS_MAX_RESCALE]; /* each in [0, n_steps - n_avg]; 0 = right after the lift */
     int energy_every;                     /* E_pot is computed on steps divisible by this (>= 1) */
     double drift_tol;                     /* per-atom production drift that sets MDEOS_CELL_DRIFT */
+    int ensemble;                         /* MDEOS_NVE_REPIN (default) or MDEOS_NVT_LANGEVIN */
+    double gamma;                         /* Langevin friction for MDEOS_NVT_LANGEVIN (>= 0) */
 } mdeos_schedule;
+
+/* Integration and equilibration (Sec. II.B, Sec. III).
+ * MDEOS_NVE_REPIN: velocity Verlet; at each rescale step the kinetic energy
+ *   is set to N e - (E_pot - E_cold) (Eq. Tcontribution with the
+ *   instantaneous E_pot); production is energy-conserving.
+ * MDEOS_NVT_LANGEVIN: the GJF Langevin integrator (friction gamma, unit
+ *   mass) thermostats at T_th, first 2 N e / N_DOF (all energy kinetic). At
+ *   each rescale step, Eq. Tcontribution with E_pot averaged over the second
+ *   half of the segment since the previous one (steps divisible by
+ *   energy_every, and the rescale step itself) gives the new temperature; the
+ *   velocities are scaled to it and it becomes T_th. Production is canonical
+ *   at the last T_th; the drift status does not apply. Noise: Philox4x64-10
+ *   keyed (seed, cell_id) at counter (atom, step, 1, 0), Box-Muller giving
+ *   three normal numbers per atom and step. */
+enum { MDEOS_NVE_REPIN = 0, MDEOS_NVT_LANGEVIN = 1 };
 
 /* Restricted result of one query (restricting operator, Sec. III). */
 typedef struct {

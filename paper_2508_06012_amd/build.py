@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmdeos.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["advance_a.hip", "advance_b.hip", "advance_c.hip", "advance_d.hip", "advance_e.hip", "kernels.hip", "mdeos.cpp", "serve.cpp"]
+SOURCES = ["advance_a.hip", "advance_b.hip", "advance_c.hip", "advance_d.hip", "advance_e.hip", "advance_f.hip",
+           "kernels.hip", "mdeos.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -29,14 +30,16 @@ FLAGS = [
 ]
 
 
-def _deps_mtime() -> float:
-    files = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(INCLUDE, "mdeos.h"), __file__]
+def _deps_mtime(src: str) -> float:
+    """Newest of the source itself, every header it may include, and this script."""
+    files = [os.path.join(CSRC, src), os.path.join(INCLUDE, "mdeos.h"), __file__]
+    files += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     return max(os.path.getmtime(f) for f in files)
 
 
 def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, src + ".o")
-    if not force and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime():
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime(src):
         return obj
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,7 +49,8 @@ def _compile(src: str, force: bool = True) -> str:
 
 
 def build(verbose: bool = True, force: bool = True) -> str:
-    """Compiles every source (force=False reuses objects newer than all sources)."""
+    """Compiles every source (force=False reuses each object that is newer than
+    its source and every header)."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), SOURCES))

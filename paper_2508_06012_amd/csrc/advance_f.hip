@@ -1,0 +1,9 @@
+// Instantiates the advance kernel for the launch shapes of group F (Langevin).
+#include "advance_impl.h"
+#include "variants.h"
+
+namespace mdeos {
+#define X(B, A, E, L, W, M, T) MDEOS_DEFINE_VARIANT(B, A, E, L, W, M, T)
+MDEOS_VARIANTS_F(X)
+#undef X
+}  // namespace mdeos

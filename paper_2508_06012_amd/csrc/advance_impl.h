@@ -50,13 +50,17 @@ struct Ctl {
   double K, U, W;
   int nU;
   int status;
+  // Langevin thermostat: temperature, and the E_pot window of the next
+  // temperature update (wave 0 owns them)
+  double T_th, segU;
+  int segN, seg_prev;
 };
 
 DEVI uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
 // Philox4x64-10 (Salmon et al., SC11): ten rounds, Weyl key schedule.
 DEVI void philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                     uint64_t& o0, uint64_t& o1) {
+                        uint64_t& o0, uint64_t& o1, uint64_t& o2, uint64_t& o3) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
   const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
 #pragma unroll
@@ -67,18 +71,38 @@ DEVI void philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     k0 += W0; k1 += W1;
   }
-  o0 = c0; o1 = c1;
+  o0 = c0; o1 = c1; o2 = c2; o3 = c3;
 }
 
 // Standard normal of (atom a, component c): Box-Muller on Philox words 0, 1
 // with key (seed, cell_id) and counter (3a + c, 0, 0, 0).
 DEVI double gauss(uint64_t seed, int64_t cell_id, int a, int c) {
-  uint64_t w0, w1;
-  philox4x64_10(seed, (uint64_t)cell_id, (uint64_t)(3 * a + c), 0, 0, 0, w0, w1);
+  uint64_t w0, w1, w2, w3;
+  philox4x64_10(seed, (uint64_t)cell_id, (uint64_t)(3 * a + c), 0, 0, 0, w0, w1, w2, w3);
   const double two_m53 = 1.0 / 9007199254740992.0;
   double u1 = 1.0 - (double)(w0 >> 11) * two_m53;
   double u2 = (double)(w1 >> 11) * two_m53;
   return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+// Thermostat noise of atom a at step k of query q: one Philox block with key
+// (seed, cell_id) at counter (a, k, 1, q); Box-Muller (cos, sin) on words 0-1
+// and cos on words 2-3. The uniforms are those of the definition; the
+// transform runs in FP32 on the hardware log2 / sin / cos (angles in
+// revolutions), which keeps this off the register budget of the step loop
+// (the numbers differ from an FP64 transform by about 1e-7 relative).
+DEVI void noise3(uint64_t seed, int64_t cell_id, int a, int k, int q, double& z0, double& z1, double& z2) {
+  uint64_t w0, w1, w2, w3;
+  philox4x64_10(seed, (uint64_t)cell_id, (uint64_t)a, (uint64_t)k, 1, (uint64_t)q, w0, w1, w2, w3);
+  const double two_m53 = 1.0 / 9007199254740992.0;
+  const float u1 = (float)(1.0 - (double)(w0 >> 11) * two_m53), u2 = (float)((double)(w1 >> 11) * two_m53);
+  const float u3 = (float)(1.0 - (double)(w2 >> 11) * two_m53), u4 = (float)((double)(w3 >> 11) * two_m53);
+  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2: -2 ln u = -2 ln 2 log2 u
+  const float r1 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u1));
+  const float r2 = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(u3));
+  z0 = (double)(r1 * __builtin_amdgcn_cosf(u2));
+  z1 = (double)(r1 * __builtin_amdgcn_sinf(u2));
+  z2 = (double)(r2 * __builtin_amdgcn_cosf(u4));
 }
 
 // Cross-lane moves on the DPP network (no LDS traffic). CTRL codes:
@@ -139,7 +163,7 @@ DEVI double wrap1(double x, double L) {
 // What the pair loop sums per atom besides the force.
 enum { ACC_F = 0, ACC_FW = 1, ACC_FWU = 2 };
 
-template <int BLOCK, int APT, int EXT, bool LLDS, bool MI>
+template <int BLOCK, int APT, int EXT, bool LLDS, bool MI, bool NVT>
 struct Box {
   static constexpr int NW = BLOCK / 64;
   static constexpr int SENT = EXT - 1;  // padding neighbour index
@@ -170,6 +194,15 @@ struct Box {
   // the cell record, which would otherwise force these to be re-read)
   int n_steps, n_avg, n_blocks, energy_every, debug_energy, n_rescale;
   int rescale_at[MDEOS_MAX_RESCALE];
+  // Langevin (GJF) in half-step form: c = gamma dt / 2, b = 1 / (1 + c),
+  // a = (1 - c) / (1 + c); u = sqrt(b) (v + dt f / 2 + beta / 2),
+  // x += sqrt(b) dt u, v = (a / sqrt(b)) u + dt f' / 2 + beta / 2, which is
+  // the two-line GJF step since (a + 1) / 2 = b
+  static constexpr bool nvt = NVT;  // Langevin (GJF) integration; else velocity Verlet
+  double gjf_sb, gjf_a_sb, gamma_dt2;
+  int query;
+  uint64_t seed;
+  int64_t cell_id;
   bool kahan;    // per-atom energy/virial sums in compensated FP32 (uniform)
 
   // owned atoms: a = t + k BLOCK
@@ -241,6 +274,23 @@ struct Box {
     n_rescale = c->n_rescale;
 #pragma unroll
     for (int r = 0; r < MDEOS_MAX_RESCALE; ++r) rescale_at[r] = r < n_rescale ? c->rescale_steps[r] : -1;
+    seed = c->seed;
+    cell_id = c->cell_id;
+    {
+      const double cg = 0.5 * c->gamma * dt, b = 1.0 / (1.0 + cg), a = (1.0 - cg) / (1.0 + cg);
+      gjf_sb = sqrt(b);
+      gjf_a_sb = a / gjf_sb;
+      gamma_dt2 = 2.0 * c->gamma * dt;
+    }
+    query = c->query;
+  }
+  // first scheduled step >= k, or -1
+  DEVI int next_update(int k) const {
+    int best = -1;
+#pragma unroll
+    for (int r = 0; r < MDEOS_MAX_RESCALE; ++r)
+      if (rescale_at[r] >= k && (best < 0 || rescale_at[r] < best)) best = rescale_at[r];
+    return best;
   }
 
   // --- block helpers --------------------------------------------------------
@@ -758,6 +808,15 @@ struct Box {
       }
       if (k == w0) ctl->E_w0 = K + U;
       if (k == n) ctl->E_n = K + U;
+      if (nvt) {
+        // E_pot window of the next temperature update: second half of the
+        // segment since the previous one
+        const int s = next_update(k), prev = ctl->seg_prev;
+        if (s >= 0 && k > prev + (s - prev) / 2 && (k % energy_every == 0 || k == s)) {
+          ctl->segU += U;
+          ctl->segN += 1;
+        }
+      }
     }
   }
 
@@ -829,6 +888,7 @@ struct Box {
       ctl->status = c->status;
       ctl->stop = 0;
       ctl->overflow = 0;
+      ctl->T_th = c->T_th; ctl->segU = c->segU; ctl->segN = c->segN; ctl->seg_prev = c->seg_prev;
     }
   }
   DEVI void clear_acc() {
@@ -840,6 +900,10 @@ struct Box {
       ctl->status = 0;
       ctl->stop = 0;
       ctl->overflow = 0;
+      ctl->T_th = c->T_th;  // the host's first guess, 2 N e / N_DOF
+      ctl->segU = 0.0;
+      ctl->segN = 0;
+      ctl->seg_prev = 0;
     }
   }
   DEVI void store_acc(int step, int phase) {
@@ -853,6 +917,7 @@ struct Box {
       c->status = ctl->status;
       c->step = step;
       c->phase = phase;
+      c->T_th = ctl->T_th; c->segU = ctl->segU; c->segN = ctl->segN; c->seg_prev = ctl->seg_prev;
     }
   }
 
@@ -981,6 +1046,9 @@ struct Box {
           vx[k] *= lam; vy[k] *= lam; vz[k] *= lam;
         }
         K = kinetic_now();
+        // a step-0 temperature update has no sampled window: with the
+        // instantaneous E_pot it is this same re-pin, T = 2 K_t / N_DOF
+        if (nvt && t == 0) ctl->T_th = 2.0 * Kt / Ndof;
       }
     }
     if (wv == 0) observe(0, K, W0, U0, true);
@@ -1097,15 +1165,29 @@ struct Box {
       const int k = step + 1;
       // kick + drift, own ghosts, displacement since the build
       float dm = 0.f;
+      // Langevin noise amplitude of this step: beta has variance 2 gamma T dt
+      const double hsig = nvt ? 0.5 * sqrt(gamma_dt2 * ctl->T_th) : 0.0;
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
         if (valid(q)) {
-          vx[q] = fma(hdt, (double)fx[q], vx[q]);
-          vy[q] = fma(hdt, (double)fy[q], vy[q]);
-          vz[q] = fma(hdt, (double)fz[q], vz[q]);
-          x[q] = fma(dt, vx[q], x[q]);
-          y[q] = fma(dt, vy[q], y[q]);
-          z[q] = fma(dt, vz[q], z[q]);
+          if (nvt) {
+            // GJF first half: u = sqrt(b) (v + dt f / 2 + beta / 2); x += sqrt(b) dt u
+            double z0, z1, z2;
+            noise3(seed, cell_id, t + q * BLOCK, k, query, z0, z1, z2);
+            vx[q] = gjf_sb * fma(hdt, (double)fx[q], fma(hsig, z0, vx[q]));
+            vy[q] = gjf_sb * fma(hdt, (double)fy[q], fma(hsig, z1, vy[q]));
+            vz[q] = gjf_sb * fma(hdt, (double)fz[q], fma(hsig, z2, vz[q]));
+            x[q] = fma(gjf_sb * dt, vx[q], x[q]);
+            y[q] = fma(gjf_sb * dt, vy[q], y[q]);
+            z[q] = fma(gjf_sb * dt, vz[q], z[q]);
+          } else {
+            vx[q] = fma(hdt, (double)fx[q], vx[q]);
+            vy[q] = fma(hdt, (double)fy[q], vy[q]);
+            vz[q] = fma(hdt, (double)fz[q], vz[q]);
+            x[q] = fma(dt, vx[q], x[q]);
+            y[q] = fma(dt, vy[q], y[q]);
+            z[q] = fma(dt, vz[q], z[q]);
+          }
           const float ex = (float)x[q] - bx[q], ey = (float)y[q] - by[q], ez = (float)z[q] - bz[q];
           dm = fmaxf(dm, ex * ex + ey * ey + ez * ez);
         }
@@ -1144,9 +1226,20 @@ struct Box {
       double ka[APT], wa[APT], ua[APT];
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
-        vx[q] = fma(hdt, (double)fx[q], vx[q]);
-        vy[q] = fma(hdt, (double)fy[q], vy[q]);
-        vz[q] = fma(hdt, (double)fz[q], vz[q]);
+        if (nvt) {
+          // GJF second half, the same noise redrawn: v = (a / sqrt(b)) u + dt f' / 2 + beta / 2
+          if (valid(q)) {
+            double z0, z1, z2;
+            noise3(seed, cell_id, t + q * BLOCK, k, query, z0, z1, z2);
+            vx[q] = fma(gjf_a_sb, vx[q], fma(hdt, (double)fx[q], hsig * z0));
+            vy[q] = fma(gjf_a_sb, vy[q], fma(hdt, (double)fy[q], hsig * z1));
+            vz[q] = fma(gjf_a_sb, vz[q], fma(hdt, (double)fz[q], hsig * z2));
+          }
+        } else {
+          vx[q] = fma(hdt, (double)fx[q], vx[q]);
+          vy[q] = fma(hdt, (double)fy[q], vy[q]);
+          vz[q] = fma(hdt, (double)fz[q], vz[q]);
+        }
         const bool v = valid(q);
         ka[q] = v ? 0.5 * (vx[q] * vx[q] + vy[q] * vy[q] + vz[q] * vz[q]) : 0.0;
         wa[q] = v ? 0.5 * wi[q] : 0.0;
@@ -1166,7 +1259,24 @@ struct Box {
             W += r[3 * g + 1];
             U += r[3 * g + 2];
           }
-          const double Kt = N * c->e - (U - Ecold);
+          double Kt;
+          if (nvt) {
+            // temperature update (Eq. Tcontribution) with E_pot averaged over
+            // the window; velocities go to that temperature, which becomes
+            // the thermostat's
+            if (k > ctl->seg_prev) {
+              ctl->segU += U;
+              ctl->segN += 1;
+            }
+            const double Ubar = ctl->segN > 0 ? ctl->segU / ctl->segN : U;
+            Kt = N * c->e - (Ubar - Ecold);
+            if (Kt > 0.0 && isfinite(Kt)) ctl->T_th = 2.0 * Kt / Ndof;
+            ctl->segU = 0.0;
+            ctl->segN = 0;
+            ctl->seg_prev = k;
+          } else {
+            Kt = N * c->e - (U - Ecold);  // energy re-pin with the instantaneous E_pot
+          }
           ctl->do_rescale = (Kt > 0.0 && isfinite(Kt)) ? 1 : 0;
           ctl->lam = (Kt > 0.0) ? sqrt(Kt / K) : 1.0;
           if (!(Kt > 0.0)) ctl->status |= ST_BELOW_COLD;
@@ -1218,10 +1328,10 @@ struct Box {
   }
 };
 
-template <int BLOCK, int APT, int EXT, bool LLDS, int WPE, bool MI>
+template <int BLOCK, int APT, int EXT, bool LLDS, int WPE, bool MI, bool NVT>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_advance(AdvanceParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
-  Box<BLOCK, APT, EXT, LLDS, MI> box(p, lds);
+  Box<BLOCK, APT, EXT, LLDS, MI, NVT> box(p, lds);
   if (threadIdx.x == 0) {
     box.PX(EXT - 1) = kSentinelPos;
     box.PY(EXT - 1) = kSentinelPos;
@@ -1243,23 +1353,24 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
 }  // namespace
 
 // Host-side wrappers of one launch shape, defined in the variant translation units.
-#define MDEOS_DEFINE_VARIANT(B, A, E, L, W, M)                                                                \
-  namespace variants {                                                                                    \
-  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M(const AdvanceParams& p, int grid, int lds, hipStream_t s) { \
-    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W, M != 0>), dim3(grid), dim3(B), lds, s, p);                  \
-    return hipGetLastError();                                                                              \
-  }                                                                                                       \
-  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M() {                                                         \
-    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W, M != 0>,                                \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                       \
-  }                                                                                                       \
-  int occ_##B##_##A##_##E##_##L##_##W##_##M(int lds) {                                                          \
-    int n = 0;                                                                                            \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0, W, M != 0>, B,    \
-                                                     lds) != hipSuccess)                                  \
-      n = 1;                                                                                              \
-    return n;                                                                                             \
-  }                                                                                                       \
+#define MDEOS_DEFINE_VARIANT(B, A, E, L, W, M, T)                                                               \
+  namespace variants {                                                                                        \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M##_##T(const AdvanceParams& p, int grid, int lds,           \
+                                                            hipStream_t s) {                                  \
+    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W, M != 0, T != 0>), dim3(grid), dim3(B), lds, s, p);         \
+    return hipGetLastError();                                                                                 \
+  }                                                                                                           \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M##_##T() {                                                  \
+    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W, M != 0, T != 0>,                       \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                          \
+  }                                                                                                           \
+  int occ_##B##_##A##_##E##_##L##_##W##_##M##_##T(int lds) {                                                   \
+    int n = 0;                                                                                                \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0, W, M != 0, T != 0>, \
+                                                     B, lds) != hipSuccess)                                   \
+      n = 1;                                                                                                  \
+    return n;                                                                                                 \
+  }                                                                                                           \
   }
 
 }  // namespace mdeos

@@ -7,10 +7,11 @@
 namespace mdeos {
 
 namespace variants {
-#define X(B, A, E, L, W, M)                                                                                  \
-  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M(const AdvanceParams& p, int grid, int lds, hipStream_t s); \
-  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M();                                                        \
-  int occ_##B##_##A##_##E##_##L##_##W##_##M(int lds);
+#define X(B, A, E, L, W, M, T)                                                                       \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M##_##T(const AdvanceParams& p, int grid, int lds,  \
+                                                            hipStream_t s);                            \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M##_##T();                                           \
+  int occ_##B##_##A##_##E##_##L##_##W##_##M##_##T(int lds);
 MDEOS_VARIANTS(X)
 #undef X
 }  // namespace variants
@@ -47,7 +48,7 @@ __global__ void k_restrict(const CellRec* cells, const int* idx, int n, DevResul
   r.Ecold = c.Ecold / c.N;
   r.drift = (c.E_n - c.E_w0) / c.N;
   int st = c.status;
-  if (fabs(r.drift) > c.drift_tol) st |= ST_DRIFT;
+  if (c.ensemble != MDEOS_NVT_LANGEVIN && fabs(r.drift) > c.drift_tol) st |= ST_DRIFT;  // energy is not conserved under a thermostat
   if (st & (ST_NONFINITE | ST_OVERFLOW)) {
     r.P = r.P_se = r.P_rms = r.T = r.T_se = r.Epot_mean = r.drift = NAN;
   }
@@ -69,7 +70,7 @@ __global__ void k_zero_ints(int* p, int n) {
 }  // namespace
 
 static const Variant kVariants[] = {
-#define X(B, A, E, L, W, M) {B, A, E, L, W, M},
+#define X(B, A, E, L, W, M, T) {B, A, E, L, W, M, T},
     MDEOS_VARIANTS(X)
 #undef X
 };
@@ -79,16 +80,14 @@ Variant variant_at(int i) { return kVariants[i]; }
 
 bool variant_available(const Variant& v) {
   for (const Variant& w : kVariants)
-    if (w.block == v.block && w.apt == v.apt && w.ext == v.ext && w.list_lds == v.list_lds && w.wpe == v.wpe &&
-        w.mi == v.mi)
-      return true;
+    if (same_variant(w, v)) return true;
   return false;
 }
 
 hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, int lds_bytes, hipStream_t s) {
-#define X(B, A, E, L, W, M)                                                                      \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M) \
-    return variants::launch_##B##_##A##_##E##_##L##_##W##_##M(p, grid, lds_bytes, s);
+#define X(B, A, E, L, W, M, T)                                                                                  \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M && v.nvt == T) \
+    return variants::launch_##B##_##A##_##E##_##L##_##W##_##M##_##T(p, grid, lds_bytes, s);
   MDEOS_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -96,17 +95,17 @@ hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, in
 
 hipError_t init_kernel_attributes() {
   hipError_t e = hipSuccess;
-#define X(B, A, E, L, W, M) \
-  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W##_##M();
+#define X(B, A, E, L, W, M, T) \
+  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W##_##M##_##T();
   MDEOS_VARIANTS(X)
 #undef X
   return e;
 }
 
 int occupancy(const Variant& v, int lds_bytes) {
-#define X(B, A, E, L, W, M)                                                                      \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M) \
-    return variants::occ_##B##_##A##_##E##_##L##_##W##_##M(lds_bytes);
+#define X(B, A, E, L, W, M, T)                                                                                  \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M && v.nvt == T) \
+    return variants::occ_##B##_##A##_##E##_##L##_##W##_##M##_##T(lds_bytes);
   MDEOS_VARIANTS(X)
 #undef X
   return 1;

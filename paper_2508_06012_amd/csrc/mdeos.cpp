@@ -196,6 +196,9 @@ extern "C" mdeos_status mdeos_validate(const mdeos_cell_spec* s, const mdeos_sch
         return set_error("rescale step outside [0, n_steps - n_avg]"), MDEOS_INVALID_ARG;
     if (q->energy_every < 1) return set_error("energy_every must be >= 1"), MDEOS_INVALID_ARG;
     if (!(q->drift_tol > 0.0)) return set_error("drift_tol must be > 0"), MDEOS_INVALID_ARG;
+    if (q->ensemble != MDEOS_NVE_REPIN && q->ensemble != MDEOS_NVT_LANGEVIN)
+      return set_error("ensemble must be MDEOS_NVE_REPIN or MDEOS_NVT_LANGEVIN"), MDEOS_INVALID_ARG;
+    if (!(std::isfinite(q->gamma) && q->gamma >= 0.0)) return set_error("gamma must be finite and >= 0"), MDEOS_INVALID_ARG;
   }
   return MDEOS_OK;
 }
@@ -311,8 +314,8 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   load_tune_cache();
   if (const char* fv = getenv("MDEOS_FORCE_VARIANT")) {
     Variant v{};
-    if (sscanf(fv, "%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi) == 6 &&
-        variant_available(v))
+    const int nf = sscanf(fv, "%d,%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi, &v.nvt);
+    if ((nf == 6 || nf == 7) && variant_available(v))
       forced_variant = v;
   }
   return MDEOS_OK;
@@ -478,6 +481,9 @@ void Ctx::fill_record(CellRec& r, const mdeos_cell_spec& s, const mdeos_schedule
   r.n_rescale = q.n_rescale;
   for (int i = 0; i < q.n_rescale; ++i) r.rescale_steps[i] = q.rescale_steps[i];
   r.energy_every = q.energy_every;
+  r.ensemble = q.ensemble;
+  r.gamma = q.gamma;
+  r.T_th = 2.0 * p.N * s.e / (3.0 * p.N - 3.0);  // first guess: all energy kinetic
   r.atom_off = atom_off;
   r.nce = p.nce;
   r.stencil = p.stencil;
@@ -501,6 +507,7 @@ mdeos_status Ctx::alloc_cells(int n, const mdeos_cell_spec* specs, const mdeos_s
     mdeos_status st = mdeos_validate(&specs[i], &q);
     if (st != MDEOS_OK) return st;
     st = plan_cell(specs[i], skin, plans[i]);
+    plans[i].nvt = q.ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;
     if (st != MDEOS_OK) {
       set_error("cell " + std::to_string(i) + ": box too large for an LDS-resident extended box");
       return st;
@@ -598,7 +605,8 @@ int Ctx::rank_variants(const CellPlan& p, std::vector<Variant>& out) const {
   for (int i = 0; i < variant_count(); ++i) {
     const Variant v = variant_at(i);
     const int lds = lds_layout(v.ext, c, v.list_lds, v.mi).total;
-    if (v.mi != p.minimg || v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax) continue;
+    if (v.mi != p.minimg || v.nvt != p.nvt || v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax)
+      continue;
     const int wg_by_lds = kLdsMax / lds, wg_by_regs = std::max(1, 4 * v.wpe / (v.block / 64));
     const int waves = std::min(wg_by_lds, wg_by_regs) * (v.block / 64);
     scored.push_back({-waves * 4096 + variant_score(v, p.N) * 16 + (v.list_lds ? 0 : 8) + (v.ext - p.ext_need) / 1024, i});
@@ -616,9 +624,7 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
   if (rank_variants(p, ranked) == 0) return false;
   auto fits = [&](const Variant& v) {
     for (const Variant& r : ranked)
-      if (r.block == v.block && r.apt == v.apt && r.ext == v.ext && r.list_lds == v.list_lds && r.wpe == v.wpe &&
-          r.mi == v.mi)
-        return true;
+      if (same_variant(r, v)) return true;
     return false;
   };
   if (forced_variant.block > 0 && fits(forced_variant)) {
@@ -696,6 +702,7 @@ std::string Ctx::tune_key(const CellPlan& p) const {
   char buf[128];
   snprintf(buf, sizeof(buf), "%s/N%d/rl%.2f/ext%d/list%d/cells%d/mi%d/prec%d", arch.c_str(), p.N, p.rl,
            align_up(p.ext_need, 512), align_up(p.list_cap, 16), align_up(p.ncell, 256), p.minimg, precision);
+  if (p.nvt) return std::string(buf) + "/nvt";
   return buf;
 }
 
@@ -722,7 +729,7 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int s : cells) {
     const CellPlan& p = cell_plan[s];
-    groups[{p.N * 2 + p.minimg, (int)std::lround(h_cells[s].rc * 1000.0)}].push_back(s);
+    groups[{p.N * 4 + p.minimg * 2 + p.nvt, (int)std::lround(h_cells[s].rc * 1000.0)}].push_back(s);
   }
   if (sticky)
     for (auto& kv : sticky_plans) groups[kv.first];  // keep every bucket seen before
@@ -801,7 +808,7 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
   std::string key = hdr;
   for (Bucket& b : buckets) {
     char bb[128];
-    snprintf(bb, sizeof(bb), "%d,%d,%d,%d,%d,%d,%d,%d,%d,%zu;", b.v.block, b.v.apt, b.v.ext, b.v.list_lds,
+    snprintf(bb, sizeof(bb), "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%zu;", b.v.mi, b.v.nvt, b.v.block, b.v.apt, b.v.ext, b.v.list_lds,
              b.caps.list_cap, b.caps.ncell_cap, b.caps.n_pad, b.grid, b.lds, b.gl_off);
     key += bb;
   }
@@ -819,10 +826,24 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
     const int na = std::min<int>(kAux, (int)buckets.size());
     for (int i = 0; i < na; ++i)
       if ((e = hipStreamWaitEvent(aux[i], ev_fork, 0)) != hipSuccess) return e;
+    // Longest processing time first: buckets in decreasing estimated cost,
+    // each on the stream with the least cost so far, so the largest start at
+    // once and the small ones fill in around them.
+    std::vector<double> cost(buckets.size(), 0.0), load(na, 0.0);
+    std::vector<int> order(buckets.size());
     for (size_t i = 0; i < buckets.size(); ++i) {
+      order[i] = (int)i;
+      // minimum-image pairs cost about 1.6 times more (FP64 image differences)
+      for (int c : buckets[i].cells)
+        cost[i] += (double)cell_plan[c].N * cell_plan[c].list_cap * std::max(1, h_cells[c].n_steps - h_cells[c].step) *
+                   (cell_plan[c].minimg ? 1.6 : 1.0);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int i : order) {
+      const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[q] += cost[i];
       Bucket& b = buckets[i];
-      if ((e = launch_advance(b.v, make_params(b, (int)i, step_budget), b.grid, b.lds, aux[i % kAux])) != hipSuccess)
-        return e;
+      if ((e = launch_advance(b.v, make_params(b, i, step_budget), b.grid, b.lds, aux[q])) != hipSuccess) return e;
     }
     for (int i = 0; i < na; ++i) {
       if ((e = hipEventRecord(ev_join[i], aux[i])) != hipSuccess) return e;
@@ -1044,10 +1065,12 @@ extern "C" mdeos_status mdeos_warm_start(mdeos_ctx* ctx, int n, const mdeos_hand
     CellPlan p;
     mdeos_status st = plan_cell(sp, c->skin, p);
     if (st != MDEOS_OK) return set_error("warm target too large"), st;
+    p.nvt = sched->ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;
     const double Lold = r.Lw;
-    const int off = r.atom_off;
+    const int off = r.atom_off, query = r.query;
     c->fill_record(r, sp, *sched, p, off);
     r.warm_scale = p.Lw / Lold;
+    r.query = query + 1;
     r.phase = PH_WARM;
     c->cell_plan[slot] = p;
   }

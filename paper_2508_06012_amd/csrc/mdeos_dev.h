@@ -64,7 +64,13 @@ struct alignas(16) CellRec {
   double K, U, W;      // values of the last completed step
   double pair_sum;     // ordered in-range pairs summed over sampled (energy) steps
   int pair_steps;      // number of sampled steps
-  int pad1;
+  int ensemble;        // MDEOS_NVE_REPIN or MDEOS_NVT_LANGEVIN
+  double gamma;        // Langevin friction
+  double T_th;         // thermostat temperature (Langevin)
+  double segU;         // E_pot summed over the current temperature-update window
+  int segN, seg_prev;  // its sample count; the previous update step
+  int query;           // queries of this cell before this one (warm starts); thermostat noise stream
+  int pad2;
 };
 
 // Result in the layout of mdeos_result.
@@ -147,8 +153,12 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
 // the neighbour list lives, the waves per SIMD the registers must allow, and
 // minimum image (no ghosts) for large boxes.
 struct Variant {
-  int block, apt, ext, list_lds, wpe, mi;
+  int block, apt, ext, list_lds, wpe, mi, nvt;
 };
+inline bool same_variant(const Variant& a, const Variant& b) {
+  return a.block == b.block && a.apt == b.apt && a.ext == b.ext && a.list_lds == b.list_lds && a.wpe == b.wpe &&
+         a.mi == b.mi && a.nvt == b.nvt;
+}
 
 // Host entry points implemented in kernels.hip.
 hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, int lds_bytes, hipStream_t s);

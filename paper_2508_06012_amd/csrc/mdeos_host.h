@@ -37,6 +37,7 @@ struct CellPlan {
   int lds_bytes = 0;
   int multi_image = 0;
   int minimg = 0;  // 1: minimum-image variant (no ghosts)
+  int nvt = 0;     // 1: Langevin integration (set from the schedule, not by plan_cell)
 };
 
 mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out);

@@ -48,9 +48,9 @@ void Ctx::load_tune_cache() {
     size_t lb = s.find('[', j), rb = s.find(']', j);
     if (lb == std::string::npos || rb == std::string::npos) break;
     Variant v{};
-    if (sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d , %d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe,
-               &v.mi) == 6 &&
-        variant_available(v))
+    const int nf = sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d , %d , %d", &v.block, &v.apt, &v.ext,
+                          &v.list_lds, &v.wpe, &v.mi, &v.nvt);
+    if ((nf == 6 || nf == 7) && variant_available(v))
       tuned[key] = v;
     i = rb + 1;
   }
@@ -66,7 +66,7 @@ void Ctx::save_tune_cache() {
     size_t k = 0;
     for (auto& kv : tuned) {
       f << "  \"" << kv.first << "\": [" << kv.second.block << ", " << kv.second.apt << ", " << kv.second.ext << ", "
-        << kv.second.list_lds << ", " << kv.second.wpe << ", " << kv.second.mi << "]"
+        << kv.second.list_lds << ", " << kv.second.wpe << ", " << kv.second.mi << ", " << kv.second.nvt << "]"
         << (++k < tuned.size() ? "," : "") << "\n";
     }
     f << "}\n";
@@ -241,7 +241,9 @@ void Ctx::serve_loop() {
       const ServeQuery q = *it;
       mdeos_cell_spec sp{q.rho, q.e, q.n_c, cfg.rc, cfg.dt, cfg.seed, q.cell_id};
       CellPlan p;
-      if (plan_cell(sp, skin, p) != MDEOS_OK) {
+      const mdeos_status pst = plan_cell(sp, skin, p);
+      p.nvt = cfg.warm.ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;  // used by warm starts (cold ones re-plan)
+      if (pst != MDEOS_OK) {
         ServeDone d{q.ticket, {}, mono_now() - serve_t0};
         d.res.status = MDEOS_CELL_OVERFLOW;
         d.res.P = d.res.T = NAN;
@@ -285,9 +287,10 @@ void Ctx::serve_loop() {
       } else {
         CellRec& r = h_cells[sc.slot];
         const double Lold = r.Lw;
-        const int off = r.atom_off;
+        const int off = r.atom_off, query = r.query;
         fill_record(r, sp, cfg.warm, p, off);
         r.warm_scale = p.Lw / Lold;
+        r.query = query + 1;
         r.phase = PH_WARM;
         cell_plan[sc.slot] = p;
       }

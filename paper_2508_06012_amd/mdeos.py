@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmdeos.so")
 OK, INVALID_ARG, OUT_OF_MEMORY, DEVICE_ERROR, NOT_READY, ADMISSION_FULL, NO_DEVICE = 0, -1, -2, -3, -4, -5, -6
 CELL_NONFINITE, CELL_ENERGY_BELOW_COLD, CELL_DRIFT, CELL_OVERFLOW, CELL_COLD_RELIFT = 1, 2, 4, 8, 16
 PREC_FP64, PREC_KAHAN = 0, 1
+NVE_REPIN, NVT_LANGEVIN = 0, 1
 MAX_RESCALE = 8
 
 
@@ -30,7 +31,8 @@ class CellSpec(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("n_steps", C.c_int), ("n_avg", C.c_int), ("n_blocks", C.c_int), ("n_rescale", C.c_int),
-                ("rescale_steps", C.c_int * MAX_RESCALE), ("energy_every", C.c_int), ("drift_tol", C.c_double)]
+                ("rescale_steps", C.c_int * MAX_RESCALE), ("energy_every", C.c_int), ("drift_tol", C.c_double),
+                ("ensemble", C.c_int), ("gamma", C.c_double)]
 
 
 class Result(C.Structure):
@@ -166,13 +168,14 @@ def _dp(a: np.ndarray | None):
 # --- builders ---------------------------------------------------------------
 
 def make_schedule(n_steps: int, n_avg: int, rescale_steps=(), n_blocks: int = 10, energy_every: int = 10,
-                  drift_tol: float = 0.05) -> Schedule:
+                  drift_tol: float = 0.05, ensemble: int = 0, gamma: float = 0.0) -> Schedule:
     s = Schedule()
     s.n_steps, s.n_avg, s.n_blocks = n_steps, n_avg, n_blocks
     s.n_rescale = len(rescale_steps)
     for i, k in enumerate(rescale_steps):
         s.rescale_steps[i] = int(k)
     s.energy_every, s.drift_tol = energy_every, drift_tol
+    s.ensemble, s.gamma = ensemble, gamma
     return s
 
 

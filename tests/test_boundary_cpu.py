@@ -1,5 +1,6 @@
 """The C-ABI library on the host: it loads, exports every declared entry point,
 validates queries and plans boxes without a device."""
+import ctypes as C
 import os
 import re
 
@@ -103,3 +104,20 @@ def test_config_layout_matches_header():
     body = hdr[hdr.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
     names = re.findall(r"\b(\w+);", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
     assert names == [f[0] for f in m.Config._fields_]
+
+
+def test_schedule_layout_matches_header():
+    hdr = open(os.path.join(ROOT, "include", "mdeos.h")).read()
+    end = hdr.index("} mdeos_schedule;")
+    body = hdr[hdr.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    names = re.findall(r"\b(\w+)(?:\[\w+\])?;", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+    assert names == [f[0] for f in m.Schedule._fields_]
+
+
+@pytest.mark.parametrize("ensemble,gamma,ok", [(0, 0.0, True), (1, 1.0, True), (1, 0.0, True), (2, 1.0, False),
+                                               (1, -0.5, False), (1, float("nan"), False)])
+def test_validate_ensemble_and_friction(ensemble, gamma, ok):
+    spec = m.make_specs(0.8, 1.5, 4, 2.5, 0.005, 1, 0)[0]
+    sch = m.make_schedule(100, 50, (10,), ensemble=ensemble, gamma=gamma)
+    st = m.lib().mdeos_validate(C.byref(spec), C.byref(sch))
+    assert (st == m.OK) == ok

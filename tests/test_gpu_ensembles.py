@@ -40,7 +40,8 @@ def test_replica_mean_matches_oracle(name, prec):
     try:
         specs = m.make_specs(np.full(M, s["rho"]), np.full(M, s["e"]), s["n_c"], s["rc"], s["dt"],
                              np.arange(s["seed0"], s["seed0"] + M), s["cell_id"])
-        sch = m.make_schedule(s["n_steps"], s["n_avg"], tuple(s["rescale_steps"]), s["n_blocks"], s["energy_every"])
+        sch = m.make_schedule(s["n_steps"], s["n_avg"], tuple(s["rescale_steps"]), s["n_blocks"], s["energy_every"],
+                              ensemble=s.get("ensemble", 0), gamma=s.get("gamma", 0.0))
         res = m.mdeos_eval_batch(ctx, specs, sch)
     finally:
         m.mdeos_destroy(ctx)

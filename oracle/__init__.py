@@ -76,6 +76,7 @@ class _Result(C.Structure):
         ("Epot_mean", C.c_double),
         ("Ecold", C.c_double),
         ("drift", C.c_double),
+        ("stress", C.c_double * 6),
         ("n_samples", C.c_int),
         ("status", C.c_int),
     ]
@@ -99,6 +100,7 @@ def lib():
         _lib.orc_box_length.restype = C.c_double
         _lib.orc_lattice.argtypes = [C.c_int, C.c_double, dp]
         _lib.orc_forces.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
+        _lib.orc_forces_tensor.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp, dp]
         _lib.orc_forces_celllist.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
         _lib.orc_forces_celllist.restype = C.c_int
         _lib.orc_ecold.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
@@ -174,6 +176,7 @@ class Result:
     Epot_mean: float
     Ecold: float
     drift: float
+    stress: tuple  # <sigma> (xx, yy, zz, xy, xz, yz), Eq. stress, over the sampled window steps
     n_samples: int
     status: int
 
@@ -238,6 +241,17 @@ def forces(x: np.ndarray, L: float, rc: float, eps: float = 1.0):
     return F, U.value, W.value
 
 
+def virial_tensor(x: np.ndarray, L: float, rc: float, eps: float = 1.0) -> np.ndarray:
+    """Pair virial tensor sum over pairs of d_a f_b, as (xx, yy, zz, xy, xz, yz)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    F = np.zeros_like(x)
+    U = C.c_double()
+    W = C.c_double()
+    S = np.zeros(6)
+    lib().orc_forces_tensor(x.shape[0], L, rc, eps, _dp(x), _dp(F), C.byref(U), C.byref(W), _dp(S))
+    return S
+
+
 def forces_celllist(x: np.ndarray, L: float, rc: float, eps: float = 1.0):
     x = np.ascontiguousarray(x, dtype=np.float64)
     F = np.zeros_like(x)
@@ -290,7 +304,7 @@ def run(cell: Cell, sched: Schedule, x=None, v=None, Ecold_total=None, n_recF: i
         C.byref(c), C.byref(s), Ecold_total, _dp(x), _dp(v),
         _dp(K), _dp(U), _dp(W), _dp(P), _dp(T), n_recF, _dp(F) if n_recF > 0 else None, C.byref(res),
     )
-    r = Result(*(getattr(res, f[0]) for f in _Result._fields_))
+    r = Result(*((tuple(getattr(res, f[0])) if f[0] == "stress" else getattr(res, f[0])) for f in _Result._fields_))
     return Run(x, v, K, U, W, P, T, F, r, Ecold_total)
 
 

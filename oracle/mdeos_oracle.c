@@ -64,6 +64,7 @@ typedef struct {
 
 typedef struct {
     double P, P_se, P_rms, T, T_se, Epot_mean, Ecold, drift;
+    double stress[6]; /* <sigma> (xx, yy, zz, xy, xz, yz) of Eq. stress over the sampled window steps */
     int n_samples, status;
 } orc_result;
 
@@ -175,7 +176,7 @@ void orc_lattice(int n_c, double rho, double *x)
  * of Eq. stress divided by three (Sec. III).
  * ------------------------------------------------------------------------- */
 static void pair_term(double dx, double dy, double dz, double rc, double eps,
-                      int i, int j, double *F, double *U, double *W)
+                      int i, int j, double *F, double *U, double *W, double *S)
 {
     double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < rc * rc)) return;
@@ -189,15 +190,23 @@ static void pair_term(double dx, double dy, double dz, double rc, double eps,
     F[3 * j + 0] -= ff * dx; F[3 * j + 1] -= ff * dy; F[3 * j + 2] -= ff * dz;
     *U += phi;
     *W += ff * r2;
+    if (S) {
+        /* virial part of Eq. stress in pair form: sum over pairs of d_a f_b, f = ff d */
+        S[0] += ff * dx * dx; S[1] += ff * dy * dy; S[2] += ff * dz * dz;
+        S[3] += ff * dx * dy; S[4] += ff * dx * dz; S[5] += ff * dy * dz;
+    }
 }
 
 /* All pairs i < j. When rc <= L/2 exactly one periodic image can be in range
  * and the minimum image (round half to even) is used; otherwise every image
  * n in {-1,0,1}^3 is tried (rc < L keeps self-images out of range). */
-void orc_forces(int N, double L, double rc, double eps, const double *x,
-                double *F, double *U_out, double *W_out)
+/* Forces, E_pot, the scalar virial W and, if S is not NULL, the virial
+ * tensor S[6] = (xx, yy, zz, xy, xz, yz) of the pairs in range. */
+void orc_forces_tensor(int N, double L, double rc, double eps, const double *x,
+                       double *F, double *U_out, double *W_out, double *S)
 {
     double U = 0.0, W = 0.0;
+    if (S) memset(S, 0, sizeof(double) * 6);
     memset(F, 0, sizeof(double) * 3 * (size_t)N);
     if (eps != 0.0) {
         int multi = rc > 0.5 * L;
@@ -210,17 +219,23 @@ void orc_forces(int N, double L, double rc, double eps, const double *x,
                     d0 -= L * nearbyint(d0 / L);
                     d1 -= L * nearbyint(d1 / L);
                     d2 -= L * nearbyint(d2 / L);
-                    pair_term(d0, d1, d2, rc, eps, i, j, F, &U, &W);
+                    pair_term(d0, d1, d2, rc, eps, i, j, F, &U, &W, S);
                 } else {
                     for (int n0 = -1; n0 <= 1; ++n0)
                         for (int n1 = -1; n1 <= 1; ++n1)
                             for (int n2 = -1; n2 <= 1; ++n2)
-                                pair_term(d0 + n0 * L, d1 + n1 * L, d2 + n2 * L, rc, eps, i, j, F, &U, &W);
+                                pair_term(d0 + n0 * L, d1 + n1 * L, d2 + n2 * L, rc, eps, i, j, F, &U, &W, S);
                 }
             }
     }
     *U_out = U;
     *W_out = W;
+}
+
+void orc_forces(int N, double L, double rc, double eps, const double *x,
+                double *F, double *U_out, double *W_out)
+{
+    orc_forces_tensor(N, L, rc, eps, x, F, U_out, W_out, NULL);
 }
 
 /* An independent route to the same pair set: a linked-cell list with cells of
@@ -277,7 +292,7 @@ int orc_forces_celllist(int N, double L, double rc, double eps, const double *x,
                         double d0 = x[3 * i + 0] - (x[3 * j + 0] + shift[0]);
                         double d1 = x[3 * i + 1] - (x[3 * j + 1] + shift[1]);
                         double d2 = x[3 * i + 2] - (x[3 * j + 2] + shift[2]);
-                        pair_term(d0, d1, d2, rc, eps, i, j, F, &U, &W);
+                        pair_term(d0, d1, d2, rc, eps, i, j, F, &U, &W, NULL);
                     }
                 }
     }
@@ -393,6 +408,8 @@ static int next_update(const orc_sched *s, int k)
  * paper's update applied to the instantaneous E_pot. K_t <= 0 flags the cell.
  * Restriction (Sec. III, Eq. stress): P_k = (2 K_k + W_k) / (3 V) is one third
  * of the trace (kinetic part m v v, virial part r f), T_k = 2 K_k / N_DOF.
+ * The full tensor of Eq. stress (kinetic m v v plus pair virial d f over V,
+ * six components) is averaged over the window steps where E_pot is sampled.
  * Samples k = n - n_avg + 1 .. n are averaged; the standard error uses
  * contiguous blocks; P_rms is the RMS deviation of the instantaneous P from
  * its mean (the fluctuation measure of Sec. IV).
@@ -446,8 +463,10 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
     double *Fold = (double *)malloc(sizeof(double) * 3 * N);
     int prev = 0, segN = 0;
     double segU = 0.0;
+    double S[6], sig[6] = {0, 0, 0, 0, 0, 0};
+    int nS = 0;
 
-    orc_forces(N, L, cell->rc, sch->eps, x, F, &U, &W);
+    orc_forces_tensor(N, L, cell->rc, sch->eps, x, F, &U, &W, S);
     K = kinetic(N, v);
     for (int k = 0; k <= n; ++k) {
         if (k > 0 && !nvt) {
@@ -457,7 +476,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
                 x[i] -= L * floor(x[i] / L);
                 if (x[i] >= L) x[i] = 0.0;
             }
-            orc_forces(N, L, cell->rc, sch->eps, x, F, &U, &W);
+            orc_forces_tensor(N, L, cell->rc, sch->eps, x, F, &U, &W, S);
             for (int i = 0; i < 3 * N; ++i) v[i] += 0.5 * dt * F[i];
             K = kinetic(N, v);
         } else if (k > 0) {
@@ -473,7 +492,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
                 if (x[i] >= L) x[i] = 0.0;
                 Fold[i] = F[i];
             }
-            orc_forces(N, L, cell->rc, sch->eps, x, F, &U, &W);
+            orc_forces_tensor(N, L, cell->rc, sch->eps, x, F, &U, &W, S);
             for (int i = 0; i < 3 * N; ++i) v[i] = ga * v[i] + 0.5 * dt * (ga * Fold[i] + F[i]) + gb * beta[i];
             K = kinetic(N, v);
         }
@@ -528,6 +547,15 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
             if (k % sch->energy_every == 0 || k == n) {
                 sumU += U;
                 nU += 1;
+                /* Eq. stress on the same sampled steps: (sum m v_a v_b + sum d_a f_b) / V */
+                double kv[6] = {0, 0, 0, 0, 0, 0};
+                for (int a = 0; a < N; ++a) {
+                    const double *va = v + 3 * a;
+                    kv[0] += va[0] * va[0]; kv[1] += va[1] * va[1]; kv[2] += va[2] * va[2];
+                    kv[3] += va[0] * va[1]; kv[4] += va[0] * va[2]; kv[5] += va[1] * va[2];
+                }
+                for (int c = 0; c < 6; ++c) sig[c] += (kv[c] + S[c]) / V;
+                nS += 1;
             }
         }
     }
@@ -537,6 +565,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
     if (status & ORC_NONFINITE) {
         res->P = res->P_se = res->P_rms = res->T = res->T_se = NAN;
         res->Epot_mean = res->drift = NAN;
+        for (int c = 0; c < 6; ++c) res->stress[c] = NAN;
     } else {
         orc_block_stats(sch->n_avg, Pser, sch->n_blocks, &res->P, &res->P_se);
         orc_block_stats(sch->n_avg, Tser, sch->n_blocks, &res->T, &res->T_se);
@@ -547,6 +576,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
         res->drift = (E_n - E_w0) / N;
         if (!nvt && fabs(res->drift) > sch->drift_tol) status |= ORC_DRIFT;
         res->n_samples = sch->n_avg;
+        for (int c = 0; c < 6; ++c) res->stress[c] = nS > 0 ? sig[c] / nS : NAN;
     }
     res->status = status;
     free(F);

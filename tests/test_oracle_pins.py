@@ -406,3 +406,59 @@ def test_gjf_free_particles_sample_the_exact_temperature(gamma, dt):
     t = 2 * r.K[1001:] / (3 * N)  # per-component variance of the velocities
     m, se = oracle.block_stats(t, 20)
     assert abs(m - T) <= 4 * se and abs(m - T) <= 0.02 * T, (m, se)
+
+
+# --- full stress tensor (Eq. stress) ----------------------------------------
+
+def _cluster():
+    """A compact 38-atom FCC fragment in the middle of a large box (no image
+    within rc), slightly perturbed so that no symmetry hides a component."""
+    L = 40.0
+    x = oracle.lattice(3, 1.0)
+    c = x.mean(0)
+    x = x[np.linalg.norm(x - c, axis=1) < 2.6]
+    x = x + np.random.default_rng(4).normal(scale=0.05, size=x.shape) + (L / 2 - c)
+    return x, L
+
+
+@pytest.mark.parametrize("a,b", [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)])
+def test_virial_tensor_is_minus_the_strain_derivative(a, b):
+    """For an isolated cluster and the affine map x_a -> x_a + e x_b,
+    dE/de = sum over pairs phi'(r) d_a d_b / r = -sum d_a f_b: the virial
+    tensor component (a, b) is minus the strain derivative of E_pot. Central
+    differences of E_pot (the pinned scalar path) fix each component's index
+    mapping and sign."""
+    x, L = _cluster()
+    rc = 2.5
+    comp = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}[(a, b)]
+    S = oracle.virial_tensor(x, L, rc)
+    h = 1e-6
+    E = []
+    for e in (h, -h):
+        y = x.copy()
+        y[:, a] += e * (x[:, b] - L / 2)
+        E.append(oracle.forces(y, L, rc)[1])
+    dE = (E[0] - E[1]) / (2 * h)
+    assert S[comp] == pytest.approx(-dE, rel=1e-6, abs=1e-7)
+
+
+def test_virial_tensor_trace_is_the_scalar_virial():
+    cell = oracle.Cell(rho=0.9, e=2.0, n_c=3, rc=2.5, dt=0.004, seed=1, cell_id=2)
+    r = oracle.run(cell, oracle.Schedule(50, 10, n_blocks=2))
+    L = oracle.box_length(3, 0.9)
+    S = oracle.virial_tensor(r.x, L, 2.5)
+    W = oracle.forces(r.x, L, 2.5)[2]
+    assert S[0] + S[1] + S[2] == pytest.approx(W, rel=1e-12)
+
+
+def test_stress_of_an_equilibrium_liquid_is_isotropic():
+    """<sigma> of a liquid: equal diagonal, vanishing shear, trace/3 = <P>
+    (on the sampled steps, within the statistical error of the averages)."""
+    cell = oracle.Cell(rho=0.7, e=float(1.5 * 2.0 * (1 - 1 / 256)), n_c=4, rc=2.5, dt=0.005, seed=9, cell_id=0)
+    r = oracle.run(cell, oracle.Schedule(3000, 2500, rescale_steps=(250, 500), energy_every=1))
+    s = np.array(r.result.stress)
+    P = r.result.P
+    se = 4 * max(r.result.P_se, 1e-3)
+    assert np.all(np.abs(s[:3] - P) < 3 * se), (s, P, se)
+    assert np.all(np.abs(s[3:]) < 3 * se), (s, se)
+    assert s[:3].mean() == pytest.approx(P, abs=1e-9)  # every window step sampled: trace/3 is P exactly

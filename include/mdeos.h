@@ -112,6 +112,9 @@ typedef struct {
     int max_list;      /* largest neighbour count seen (capacity diagnostics) */
     int max_ext;       /* largest real + ghost atom count seen */
     int reserved;
+    double stress[6];  /* <sigma> of Eq. stress, (xx, yy, zz, xy, xz, yz): (sum m v_a v_b + sum over pairs
+                          d_a f_b) / V, pressure convention (trace / 3 = P), averaged over the window
+                          steps where E_pot is sampled */
 } mdeos_result;
 
 typedef struct {

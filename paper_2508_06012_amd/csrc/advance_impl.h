@@ -54,6 +54,9 @@ struct Ctl {
   // temperature update (wave 0 owns them)
   double T_th, segU;
   int segN, seg_prev;
+  // stress tensor sums over the sampled window steps (thread 0 owns them)
+  double sigK[6], sigV[6];
+  int nS;
 };
 
 DEVI uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
@@ -161,7 +164,7 @@ DEVI double wrap1(double x, double L) {
 // tile [0, L) periodically and every pair takes its nearest periodic image
 // (boxes with L >= 3 rl whose ghost-extended box would not fit in LDS).
 // What the pair loop sums per atom besides the force.
-enum { ACC_F = 0, ACC_FW = 1, ACC_FWU = 2 };
+enum { ACC_F = 0, ACC_FW = 1, ACC_FWU = 2, ACC_FWUS = 3 };
 
 template <int BLOCK, int APT, int EXT, bool LLDS, bool MI, bool NVT>
 struct Box {
@@ -211,6 +214,7 @@ struct Box {
   double x[APT], y[APT], z[APT], vx[APT], vy[APT], vz[APT];
   float fx[APT], fy[APT], fz[APT], bx[APT], by[APT], bz[APT];
   double wi[APT], ui[APT];
+  float sv[6][APT];  // per-atom pair virial tensor of a sampled step (xx, yy, zz, xy, xz, yz)
   int gofs[APT], gmask[APT], nblk[APT], cnt_in[APT];
   double pairs_t;  // ordered in-range pairs of this thread's atoms over sampled steps
   int esteps;      // sampled (energy) steps in this launch
@@ -367,6 +371,28 @@ struct Box {
     B = ctl->scal[1];
     C = ctl->scal[2];
     __syncthreads();
+  }
+
+  // Adds the block sums of six per-atom values (groups summed in index order,
+  // FP64) to acc6 (thread 0).
+  DEVI void tensor_add(const double (&a)[6][APT], double* acc6) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      group_sums(a[3 * h], a[3 * h + 1], a[3 * h + 2], red);
+      __syncthreads();
+      if (t == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int g = 0; g < G; ++g) {
+          s0 += red[3 * g + 0];
+          s1 += red[3 * g + 1];
+          s2 += red[3 * g + 2];
+        }
+        acc6[3 * h + 0] += s0;
+        acc6[3 * h + 1] += s1;
+        acc6[3 * h + 2] += s2;
+      }
+      __syncthreads();
+    }
   }
 
   DEVI bool valid(int k) const { return t + k * BLOCK < N; }
@@ -667,6 +693,7 @@ struct Box {
       float ax = 0.f, ay = 0.f, az = 0.f;
       double wd = 0.0, ud = 0.0;                  // FP64 sums
       float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;  // Kahan sums and compensations
+      float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;  // virial tensor
       int cin = 0;
       const int nb = nblk[k];
       // one block of 8 list entries (two 16-bit byte offsets per word)
@@ -693,9 +720,23 @@ struct Box {
           const float ir6 = ir2 * ir2 * ir2;
           const float vir = fmaf(48.0f, ir6, -24.0f) * ir6;
           const float ff = vir * ir2;
-          ax = fmaf(ff, dx, ax);
-          ay = fmaf(ff, dy, ay);
-          az = fmaf(ff, dz, az);
+          if (ACC == ACC_FWUS) {
+            // pair virial tensor d_a f_b with f = ff d (six components)
+            const float fdx = ff * dx, fdy = ff * dy, fdz = ff * dz;
+            ax += fdx;
+            ay += fdy;
+            az += fdz;
+            sxx = fmaf(fdx, dx, sxx);
+            syy = fmaf(fdy, dy, syy);
+            szz = fmaf(fdz, dz, szz);
+            sxy = fmaf(fdx, dy, sxy);
+            sxz = fmaf(fdx, dz, sxz);
+            syz = fmaf(fdy, dz, syz);
+          } else {
+            ax = fmaf(ff, dx, ax);
+            ay = fmaf(ff, dy, ay);
+            az = fmaf(ff, dz, az);
+          }
           if (ACC >= ACC_FW) {
             if (KAHAN) {
               const float y1 = vir - wc, t1 = ws + y1;
@@ -705,7 +746,7 @@ struct Box {
               wd += (double)vir;
             }
           }
-          if (ACC == ACC_FWU) {
+          if (ACC >= ACC_FWU) {
             const float e = fmaf(ir6, ir6, -ir6);
             if (KAHAN) {
               const float y2 = e - uc, t2 = us + y2;
@@ -747,8 +788,12 @@ struct Box {
         ud = (double)us - (double)uc;
       }
       wi[k] = ACC >= ACC_FW ? wd : 0.0;
-      ui[k] = ACC == ACC_FWU ? 4.0 * ud - (double)cin * u_shift : 0.0;
-      cnt_in[k] = (ACC == ACC_FWU && a < N) ? cin : 0;
+      ui[k] = ACC >= ACC_FWU ? 4.0 * ud - (double)cin * u_shift : 0.0;
+      cnt_in[k] = (ACC >= ACC_FWU && a < N) ? cin : 0;
+      if (ACC == ACC_FWUS) {
+        sv[0][k] = sxx; sv[1][k] = syy; sv[2][k] = szz;
+        sv[3][k] = sxy; sv[4][k] = sxz; sv[5][k] = syz;
+      }
     }
   }
   template <int ACC>
@@ -889,6 +934,11 @@ struct Box {
       ctl->stop = 0;
       ctl->overflow = 0;
       ctl->T_th = c->T_th; ctl->segU = c->segU; ctl->segN = c->segN; ctl->seg_prev = c->seg_prev;
+      for (int q = 0; q < 6; ++q) {
+        ctl->sigK[q] = c->sigK[q];
+        ctl->sigV[q] = c->sigV[q];
+      }
+      ctl->nS = c->nS;
     }
   }
   DEVI void clear_acc() {
@@ -904,6 +954,8 @@ struct Box {
       ctl->segU = 0.0;
       ctl->segN = 0;
       ctl->seg_prev = 0;
+      for (int q = 0; q < 6; ++q) ctl->sigK[q] = ctl->sigV[q] = 0.0;
+      ctl->nS = 0;
     }
   }
   DEVI void store_acc(int step, int phase) {
@@ -918,6 +970,11 @@ struct Box {
       c->step = step;
       c->phase = phase;
       c->T_th = ctl->T_th; c->segU = ctl->segU; c->segN = ctl->segN; c->seg_prev = ctl->seg_prev;
+      for (int q = 0; q < 6; ++q) {
+        c->sigK[q] = ctl->sigK[q];
+        c->sigV[q] = ctl->sigV[q];
+      }
+      c->nS = ctl->nS;
     }
   }
 
@@ -1213,7 +1270,20 @@ struct Box {
         __syncthreads();
       }
       const bool energy = is_energy_step(k);
-      if (energy) {
+      // steps where the stress tensor of Eq. stress is sampled (as <E_pot>)
+      const bool sample = energy && k > n_steps - n_avg && (k % energy_every == 0 || k == n_steps);
+      if (sample) {
+        forces<ACC_FWUS>();
+#pragma unroll
+        for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
+        ++esteps;
+        double vt[6][APT];  // pair virial tensor, halved: full lists see each pair twice
+#pragma unroll
+        for (int q = 0; q < APT; ++q)
+#pragma unroll
+          for (int c6 = 0; c6 < 6; ++c6) vt[c6][q] = valid(q) ? 0.5 * (double)sv[c6][q] : 0.0;
+        tensor_add(vt, ctl->sigV);
+      } else if (energy) {
         forces<ACC_FWU>();
 #pragma unroll
         for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
@@ -1246,6 +1316,21 @@ struct Box {
         ua[q] = (v && energy) ? 0.5 * ui[q] : 0.0;
       }
       group_sums(ka, wa, ua, ring + (size_t)(k % RING) * 3 * p.caps.gmax);
+      if (sample) {
+        double kt[6][APT];  // kinetic tensor m v_a v_b
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          const bool v = valid(q);
+          kt[0][q] = v ? vx[q] * vx[q] : 0.0;
+          kt[1][q] = v ? vy[q] * vy[q] : 0.0;
+          kt[2][q] = v ? vz[q] * vz[q] : 0.0;
+          kt[3][q] = v ? vx[q] * vy[q] : 0.0;
+          kt[4][q] = v ? vx[q] * vz[q] : 0.0;
+          kt[5][q] = v ? vy[q] * vz[q] : 0.0;
+        }
+        tensor_add(kt, ctl->sigK);
+        if (t == 0) ctl->nS += 1;
+      }
       step = k;
       __syncthreads();
       if (is_rescale(k)) {

@@ -47,10 +47,13 @@ __global__ void k_restrict(const CellRec* cells, const int* idx, int n, DevResul
   r.Epot_mean = c.nU > 0 ? c.sumU / c.nU / c.N : NAN;
   r.Ecold = c.Ecold / c.N;
   r.drift = (c.E_n - c.E_w0) / c.N;
+  // Eq. stress: (kinetic + pair virial) / V averaged over the sampled steps
+  for (int q = 0; q < 6; ++q) r.stress[q] = c.nS > 0 ? (c.sigK[q] + c.sigV[q]) / (c.nS * c.V) : NAN;
   int st = c.status;
   if (c.ensemble != MDEOS_NVT_LANGEVIN && fabs(r.drift) > c.drift_tol) st |= ST_DRIFT;  // energy is not conserved under a thermostat
   if (st & (ST_NONFINITE | ST_OVERFLOW)) {
     r.P = r.P_se = r.P_rms = r.T = r.T_se = r.Epot_mean = r.drift = NAN;
+    for (int q = 0; q < 6; ++q) r.stress[q] = NAN;
   }
   r.pairs = c.pair_steps > 0 ? c.pair_sum / c.pair_steps : 0.0;
   r.n_samples = done;

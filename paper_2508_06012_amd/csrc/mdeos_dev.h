@@ -70,7 +70,8 @@ struct alignas(16) CellRec {
   double segU;         // E_pot summed over the current temperature-update window
   int segN, seg_prev;  // its sample count; the previous update step
   int query;           // queries of this cell before this one (warm starts); thermostat noise stream
-  int pad2;
+  int nS;              // sampled steps in the stress sums
+  double sigK[6], sigV[6];  // kinetic (sum v_a v_b) and virial (sum d_a f_b) tensors summed over them
 };
 
 // Result in the layout of mdeos_result.
@@ -78,6 +79,7 @@ struct DevResult {
   double P, P_se, P_rms, T, T_se, Epot_mean, Ecold, drift;
   double pairs;
   int n_samples, status, n_builds, max_list, max_ext, pad;
+  double stress[6];
 };
 
 // Structure-of-arrays atom state in device memory; each array has `cap` entries.

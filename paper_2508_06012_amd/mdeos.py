@@ -39,7 +39,7 @@ class Result(C.Structure):
     _fields_ = [("P", C.c_double), ("P_se", C.c_double), ("P_rms", C.c_double), ("T", C.c_double),
                 ("T_se", C.c_double), ("Epot_mean", C.c_double), ("Ecold", C.c_double), ("drift", C.c_double),
                 ("pairs", C.c_double), ("n_samples", C.c_int), ("status", C.c_int), ("n_builds", C.c_int),
-                ("max_list", C.c_int), ("max_ext", C.c_int), ("reserved", C.c_int)]
+                ("max_list", C.c_int), ("max_ext", C.c_int), ("reserved", C.c_int), ("stress", C.c_double * 6)]
 
 
 class Config(C.Structure):
@@ -68,7 +68,7 @@ class ServeStats(C.Structure):
 RESULT_DTYPE = np.dtype([("P", "f8"), ("P_se", "f8"), ("P_rms", "f8"), ("T", "f8"), ("T_se", "f8"),
                          ("Epot_mean", "f8"), ("Ecold", "f8"), ("drift", "f8"), ("pairs", "f8"),
                          ("n_samples", "i4"), ("status", "i4"), ("n_builds", "i4"), ("max_list", "i4"),
-                         ("max_ext", "i4"), ("reserved", "i4")])
+                         ("max_ext", "i4"), ("reserved", "i4"), ("stress", "f8", (6,))])
 assert RESULT_DTYPE.itemsize == C.sizeof(Result)
 
 EXPORTED = [

@@ -1,0 +1,67 @@
+"""The full stress tensor of Eq. stress on the GPU against the FP64 oracle.
+
+Both sides average sigma_ab = (sum m v_a v_b + sum over pairs d_a f_b) / V
+over the window steps where E_pot is sampled. From identical starting bits
+the two trajectories agree to ~1e-7 over 50 steps, so the six averaged
+components must agree to the force bar (the pair virial is a force moment,
+summed per atom in FP32 on the device): |d sigma_ab| <= 1e-5 max_c |sigma_cc|.
+Independently, trace / 3 equals <P> when every window step is sampled.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06012_amd import mdeos as m
+from paper_2508_06012_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (oracle.Cell(rho=0.8442, e=wl.e_from_T(1.2, 256).item(), n_c=4, rc=2.5, dt=0.005, seed=7, cell_id=1), 0),
+    (oracle.Cell(rho=1.2, e=wl.e_from_T(2.0, 108).item(), n_c=3, rc=3.0, dt=0.004, seed=7, cell_id=4), 0),
+    (oracle.Cell(rho=0.9, e=wl.e_from_T(5.0, 864).item(), n_c=6, rc=4.0, dt=0.002, seed=7, cell_id=5), 0),
+    (oracle.Cell(rho=0.6, e=wl.e_from_T(2.0, 4000).item(), n_c=10, rc=2.5, dt=0.004, seed=7, cell_id=6), 0),
+    (oracle.Cell(rho=0.8442, e=wl.e_from_T(1.5, 256).item(), n_c=4, rc=2.5, dt=0.005, seed=7, cell_id=1), 1),
+]
+IDS = ["cfg1-256", "multi-image-108", "rc4-864", "minimum-image-4000", "langevin-256"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = m.mdeos_create()
+    yield c
+    m.mdeos_destroy(c)
+
+
+@pytest.mark.parametrize("cell,ens", CASES, ids=IDS)
+def test_stress_matches_oracle_from_identical_bits(ctx, cell, ens):
+    n, na = 50, 20
+    x0, v0, Ec = oracle.lift(cell)
+    ref = oracle.run(cell, oracle.Schedule(n, na, n_blocks=2, rescale_steps=(10,), energy_every=1, ensemble=ens,
+                                           gamma=1.0), x=x0, v=v0, Ecold_total=Ec).result
+    spec = m.make_specs(cell.rho, cell.e, cell.n_c, cell.rc, cell.dt, cell.seed, cell.cell_id)[0]
+    sch = m.make_schedule(n, na, (10,), 2, 1, ensemble=ens, gamma=1.0)
+    print(f"stress {cell} ensemble {ens}", flush=True)
+    h = m.mdeos_lift_from_state(ctx, spec, sch, x0, v0)
+    m.mdeos_advance(ctx, [h], 10 ** 6)
+    g = m.mdeos_restrict(ctx, [h])[0]
+    m.mdeos_release(ctx, [h])
+    so, sg = np.array(ref.stress), np.array(g["stress"])
+    scale = np.abs(so[:3]).max()
+    err = np.abs(sg - so) / scale
+    print(f"  oracle {np.round(so, 5)}\n  gpu    {np.round(sg, 5)}\n  max err / scale {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-5, err
+
+
+def test_trace_over_three_is_the_pressure(ctx):
+    rng = np.random.default_rng(2)
+    n = 32
+    rho = rng.uniform(0.3, 1.1, size=n)
+    T = rng.uniform(0.8, 3.0, size=n)
+    nc = rng.choice([3, 4, 5], size=n)
+    specs = m.make_specs(rho, wl.e_from_T(T, 4 * nc ** 3), nc, 2.5, 0.004, 5, np.arange(n))
+    res = m.mdeos_eval_batch(ctx, specs, m.make_schedule(600, 300, (100, 200), 10, 1))
+    tr3 = res["stress"][:, :3].mean(axis=1)
+    scale = np.maximum(np.abs(res["P"]), rho * res["T"])
+    assert np.all(np.abs(tr3 - res["P"]) <= 1e-5 * scale), np.abs(tr3 - res["P"]) / scale
+    assert np.all(np.isfinite(res["stress"]))

@@ -48,6 +48,8 @@ class _Cell(C.Structure):
         ("seed", C.c_uint64),
         ("cell_id", C.c_int64),
         ("query", C.c_int64),
+        ("potential", C.c_int),
+        ("eam_c", C.c_double),
     ]
 
 
@@ -105,6 +107,9 @@ def lib():
         _lib.orc_forces_celllist.restype = C.c_int
         _lib.orc_ecold.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
         _lib.orc_ecold.restype = C.c_double
+        _lib.orc_ecold_cell.argtypes = [C.POINTER(_Cell), C.c_double]
+        _lib.orc_ecold_cell.restype = C.c_double
+        _lib.orc_forces_eam.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp, dp, dp]
         _lib.orc_lift.argtypes = [C.POINTER(_Cell), C.c_double, dp, dp]
         _lib.orc_lift.restype = C.c_double
         _lib.orc_block_stats.argtypes = [C.c_int, dp, C.c_int, dp, dp]
@@ -134,13 +139,16 @@ class Cell:
     seed: int = 20250806
     cell_id: int = 0
     query: int = 0  # index of this query of the cell (thermostat noise counter word 3)
+    potential: int = 0  # 0: LJTS; 1: embedded-atom form of Eq. Etot (Sutton-Chen (9, 6) stand-in)
+    eam_c: float = 39.432  # embedding strength c of the embedded-atom form
 
     @property
     def N(self) -> int:
         return 4 * self.n_c ** 3
 
     def _c(self) -> _Cell:
-        return _Cell(self.rho, self.e, self.n_c, self.rc, self.dt, self.seed & (2**64 - 1), self.cell_id, self.query)
+        return _Cell(self.rho, self.e, self.n_c, self.rc, self.dt, self.seed & (2**64 - 1), self.cell_id, self.query,
+                     self.potential, self.eam_c)
 
 
 @dataclass
@@ -263,6 +271,34 @@ def forces_celllist(x: np.ndarray, L: float, rc: float, eps: float = 1.0):
     return F, U.value, W.value
 
 
+def forces_eam(x: np.ndarray, L: float, rc: float, c: float):
+    """Embedded-atom form (Eq. Etot): forces, E_pot, W, virial tensor and the
+    host densities rhobar."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    F = np.zeros_like(x)
+    U = C.c_double()
+    W = C.c_double()
+    S = np.zeros(6)
+    rb = np.zeros(x.shape[0])
+    lib().orc_forces_eam(x.shape[0], L, rc, c, _dp(x), _dp(F), C.byref(U), C.byref(W), _dp(S), _dp(rb))
+    return F, U.value, W.value, S, rb
+
+
+def cell_forces(cell: "Cell", x: np.ndarray, eps: float = 1.0):
+    """Forces, E_pot and W of the cell's material at positions x."""
+    L = box_length(cell.n_c, cell.rho)
+    if cell.potential == 1:
+        F, U, W, _, _ = forces_eam(x, L, cell.rc, cell.eam_c)
+        return F, U, W
+    return forces(x, L, cell.rc, eps)
+
+
+def ecold_cell(cell: "Cell", eps: float = 1.0) -> float:
+    """Total cold energy of the cell's static lattice, for its material."""
+    c = cell._c()
+    return lib().orc_ecold_cell(C.byref(c), eps)
+
+
 def ecold(n_c: int, rho: float, rc: float, eps: float = 1.0) -> float:
     """Total cold energy of the static lattice (not per atom)."""
     return lib().orc_ecold(n_c, rho, rc, eps)
@@ -293,7 +329,7 @@ def run(cell: Cell, sched: Schedule, x=None, v=None, Ecold_total=None, n_recF: i
         x = np.array(x, dtype=np.float64, order="C", copy=True)
         v = np.array(v, dtype=np.float64, order="C", copy=True)
         if Ecold_total is None:
-            Ecold_total = ecold(cell.n_c, cell.rho, cell.rc, sched.eps)
+            Ecold_total = ecold_cell(cell, sched.eps)
     n = sched.n_steps
     K, U, W, P, T = (np.zeros(n + 1) for _ in range(5))
     F = np.zeros((max(n_recF, 0), cell.N, 3))

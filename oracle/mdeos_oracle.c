@@ -1,7 +1,8 @@
 /*
  * mdeos oracle: a plain, slow, FP64 CPU implementation of the in-line
  * molecular-dynamics equation of state (lift -> advance -> restrict) for a
- * truncated-shifted Lennard-Jones (LJTS) fluid in reduced units.
+ * truncated-shifted Lennard-Jones (LJTS) fluid in reduced units, or for a
+ * many-body material of the embedded-atom form (Eq. Etot).
  *
  * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg load this library. The product path (the HIP
@@ -47,6 +48,8 @@ typedef struct {
     uint64_t seed;   /* Philox key word 0 */
     int64_t cell_id; /* Philox key word 1 */
     int64_t query;   /* index of this query of the cell (0 for the first); thermostat counter word 3 */
+    int potential;   /* 0: LJTS (well depth from the schedule); 1: embedded-atom form (Eq. Etot) */
+    double eam_c;    /* embedding strength c of the embedded-atom form */
 } orc_cell;
 
 typedef struct {
@@ -303,6 +306,115 @@ int orc_forces_celllist(int N, double L, double rc, double eps, const double *x,
     return 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * Embedded-atom form (appendix, Eq. Etot):
+ *   E_pot = 1/2 sum_{i != j} V(r_ij) + sum_i F(rhobar_i),
+ *   rhobar_i = sum_{j != i} f(r_ij)   (the density other atoms superpose at i).
+ * The paper's Cu tables are not available; the functions are an analytic
+ * stand-in of the Finnis-Sinclair / Sutton-Chen family in reduced units
+ * (energy eps, length a = the lattice parameter of the fitted crystal):
+ *   V(r) = r^-9,  f(r) = r^-6,  F(rhobar) = -c sqrt(rhobar),
+ * with V and f truncated at rc in shifted-force form, g_s(r) = g(r) - g(rc)
+ * - (r - rc) g'(rc), so that energies and forces are continuous at rc.
+ * Forces, from E_pot's dependence on distances only, with d = x_i - x_j:
+ *   f_ij = -[V_s'(r) + (F'(rhobar_i) + F'(rhobar_j)) f_s'(r)] d / r,
+ *   V_s'(r) = -9 (r^-10 - rc^-10),  f_s'(r) = -6 (r^-7 - rc^-7),
+ *   F'(rhobar) = -c / (2 sqrt(rhobar)).
+ * The virial and the virial tensor take these pair forces exactly as in the
+ * pair-potential case (Eq. stress), which holds for any energy that depends
+ * on interatomic distances alone.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double rc, c;
+    double *rhobar;   /* sweep 0 accumulates */
+    const double *Fp; /* sweep 1 reads F'(rhobar) */
+    double *F, U, W, *S;
+} eam_acc;
+
+static void eam_pair(eam_acc *A, int sweep, double dx, double dy, double dz, int i, int j)
+{
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double rc = A->rc;
+    if (!(r2 < rc * rc)) return;
+    double r = sqrt(r2);
+    if (sweep == 0) {
+        double fr = pow(r, -6.0) - pow(rc, -6.0) + 6.0 * pow(rc, -7.0) * (r - rc);
+        A->rhobar[i] += fr;
+        A->rhobar[j] += fr;
+        return;
+    }
+    double dV = -9.0 * (pow(r, -10.0) - pow(rc, -10.0));
+    double df = -6.0 * (pow(r, -7.0) - pow(rc, -7.0));
+    double ff = -(dV + (A->Fp[i] + A->Fp[j]) * df) / r;
+    A->U += pow(r, -9.0) - pow(rc, -9.0) + 9.0 * pow(rc, -10.0) * (r - rc);
+    A->F[3 * i + 0] += ff * dx; A->F[3 * i + 1] += ff * dy; A->F[3 * i + 2] += ff * dz;
+    A->F[3 * j + 0] -= ff * dx; A->F[3 * j + 1] -= ff * dy; A->F[3 * j + 2] -= ff * dz;
+    A->W += ff * r2;
+    if (A->S) {
+        A->S[0] += ff * dx * dx; A->S[1] += ff * dy * dy; A->S[2] += ff * dz * dz;
+        A->S[3] += ff * dx * dy; A->S[4] += ff * dx * dz; A->S[5] += ff * dy * dz;
+    }
+}
+
+/* The pair set of orc_forces_tensor: all pairs i < j, minimum image when
+ * rc <= L/2, else every image in {-1,0,1}^3. */
+static void eam_sweep(eam_acc *A, int sweep, int N, double L, const double *x)
+{
+    int multi = A->rc > 0.5 * L;
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) {
+            double d0 = x[3 * i + 0] - x[3 * j + 0];
+            double d1 = x[3 * i + 1] - x[3 * j + 1];
+            double d2 = x[3 * i + 2] - x[3 * j + 2];
+            if (!multi) {
+                d0 -= L * nearbyint(d0 / L);
+                d1 -= L * nearbyint(d1 / L);
+                d2 -= L * nearbyint(d2 / L);
+                eam_pair(A, sweep, d0, d1, d2, i, j);
+            } else {
+                for (int n0 = -1; n0 <= 1; ++n0)
+                    for (int n1 = -1; n1 <= 1; ++n1)
+                        for (int n2 = -1; n2 <= 1; ++n2)
+                            eam_pair(A, sweep, d0 + n0 * L, d1 + n1 * L, d2 + n2 * L, i, j);
+            }
+        }
+}
+
+/* Forces, E_pot, W and (if S is not NULL) the virial tensor of the
+ * embedded-atom form; rhobar (N doubles, may be NULL) receives the densities. */
+void orc_forces_eam(int N, double L, double rc, double c, const double *x,
+                    double *F, double *U_out, double *W_out, double *S, double *rhobar_out)
+{
+    double *rhobar = (double *)calloc((size_t)N, sizeof(double));
+    double *Fp = (double *)malloc(sizeof(double) * (size_t)N);
+    eam_acc A = {rc, c, rhobar, Fp, F, 0.0, 0.0, S};
+    memset(F, 0, sizeof(double) * 3 * (size_t)N);
+    if (S) memset(S, 0, sizeof(double) * 6);
+    eam_sweep(&A, 0, N, L, x);
+    double Uemb = 0.0;
+    for (int i = 0; i < N; ++i) {
+        Uemb += -c * sqrt(rhobar[i]);
+        /* an atom with no neighbour in range has no pair that would use F' */
+        Fp[i] = rhobar[i] > 0.0 ? -c / (2.0 * sqrt(rhobar[i])) : 0.0;
+    }
+    eam_sweep(&A, 1, N, L, x);
+    *U_out = A.U + Uemb;
+    *W_out = A.W;
+    if (rhobar_out) memcpy(rhobar_out, rhobar, sizeof(double) * (size_t)N);
+    free(rhobar);
+    free(Fp);
+}
+
+/* The cell's material: LJTS with well depth eps, or the embedded-atom form. */
+static void cell_forces(const orc_cell *cell, double eps, int N, double L, const double *x,
+                        double *F, double *U, double *W, double *S)
+{
+    if (cell->potential == 1)
+        orc_forces_eam(N, L, cell->rc, cell->eam_c, x, F, U, W, S, NULL);
+    else
+        orc_forces_tensor(N, L, cell->rc, eps, x, F, U, W, S);
+}
+
 /* Round a double to the nearest float and back. */
 static double to_f32(double v) { return (double)(float)v; }
 
@@ -315,6 +427,21 @@ static double kinetic(int N, const double *v)
 
 /* Cold energy: potential energy of the static lattice at rho (Sec. III, the
  * energy found with near-zero velocities; read as exactly zero velocities). */
+double orc_ecold_cell(const orc_cell *cell, double eps)
+{
+    int n_c = cell->n_c;
+    int N = 4 * n_c * n_c * n_c;
+    double *x = (double *)malloc(sizeof(double) * 3 * N);
+    double *F = (double *)malloc(sizeof(double) * 3 * N);
+    double U, W;
+    orc_lattice(n_c, cell->rho, x);
+    for (int i = 0; i < 3 * N; ++i) x[i] = to_f32(x[i]);
+    cell_forces(cell, eps, N, orc_box_length(n_c, cell->rho), x, F, &U, &W, NULL);
+    free(x);
+    free(F);
+    return U;
+}
+
 double orc_ecold(int n_c, double rho, double rc, double eps)
 {
     int N = 4 * n_c * n_c * n_c;
@@ -345,7 +472,7 @@ double orc_lift(const orc_cell *cell, double eps, double *x, double *v)
     double Ndof = 3.0 * N - 3.0;
     orc_lattice(n_c, cell->rho, x);
     for (int i = 0; i < 3 * N; ++i) x[i] = to_f32(x[i]);
-    double Ecold = orc_ecold(n_c, cell->rho, cell->rc, eps);
+    double Ecold = orc_ecold_cell(cell, eps);
 
     double T0 = 2.0 * N * cell->e / Ndof;
     double mean[3] = {0.0, 0.0, 0.0};
@@ -466,7 +593,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
     double S[6], sig[6] = {0, 0, 0, 0, 0, 0};
     int nS = 0;
 
-    orc_forces_tensor(N, L, cell->rc, sch->eps, x, F, &U, &W, S);
+    cell_forces(cell, sch->eps, N, L, x, F, &U, &W, S);
     K = kinetic(N, v);
     for (int k = 0; k <= n; ++k) {
         if (k > 0 && !nvt) {
@@ -476,7 +603,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
                 x[i] -= L * floor(x[i] / L);
                 if (x[i] >= L) x[i] = 0.0;
             }
-            orc_forces_tensor(N, L, cell->rc, sch->eps, x, F, &U, &W, S);
+            cell_forces(cell, sch->eps, N, L, x, F, &U, &W, S);
             for (int i = 0; i < 3 * N; ++i) v[i] += 0.5 * dt * F[i];
             K = kinetic(N, v);
         } else if (k > 0) {
@@ -492,7 +619,7 @@ void orc_run(const orc_cell *cell, const orc_sched *sch, double Ecold_total,
                 if (x[i] >= L) x[i] = 0.0;
                 Fold[i] = F[i];
             }
-            orc_forces_tensor(N, L, cell->rc, sch->eps, x, F, &U, &W, S);
+            cell_forces(cell, sch->eps, N, L, x, F, &U, &W, S);
             for (int i = 0; i < 3 * N; ++i) v[i] = ga * v[i] + 0.5 * dt * (ga * Fold[i] + F[i]) + gb * beta[i];
             K = kinetic(N, v);
         }

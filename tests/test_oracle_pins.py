@@ -462,3 +462,152 @@ def test_stress_of_an_equilibrium_liquid_is_isotropic():
     assert np.all(np.abs(s[:3] - P) < 3 * se), (s, P, se)
     assert np.all(np.abs(s[3:]) < 3 * se), (s, se)
     assert s[:3].mean() == pytest.approx(P, abs=1e-9)  # every window step sampled: trace/3 is P exactly
+
+
+# --- embedded-atom form (Eq. Etot): Sutton-Chen (9, 6) stand-in, shifted force --
+
+EAM_C, EAM_RC = 39.432, 1.5
+
+
+def _sf(g, dg, r, rc):
+    """Shifted-force truncation written from its definition (test side)."""
+    r = np.asarray(r, dtype=float)
+    return np.where(r < rc, g(r) - g(rc) - (r - rc) * dg(rc), 0.0)
+
+
+def eam_V(r, rc):
+    return _sf(lambda s: s ** -9.0, lambda s: -9.0 * s ** -10.0, r, rc)
+
+
+def eam_f(r, rc):
+    return _sf(lambda s: s ** -6.0, lambda s: -6.0 * s ** -7.0, r, rc)
+
+
+def fcc_distances(rho, rc):
+    """|R| of every FCC lattice vector R != 0 with |R| < rc."""
+    l = (4.0 / rho) ** (1.0 / 3.0)
+    m = int(math.ceil(rc / l)) + 1
+    basis = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    g = np.arange(-m, m + 1)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1).astype(float)
+    R = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * l
+    r = np.sqrt((R ** 2).sum(axis=1))
+    return r[(r > 1e-12) & (r < rc)]
+
+
+def eam_lattice_energy(rho, rc, c=EAM_C):
+    """E/N of the perfect FCC lattice: every site sees the same density, so
+    E/N = 1/2 sum_R V(|R|) + F(sum_R f(|R|)) with F = -c sqrt."""
+    r = fcc_distances(rho, rc)
+    return 0.5 * eam_V(r, rc).sum() - c * math.sqrt(eam_f(r, rc).sum())
+
+
+def _eam_cell(rho, n_c, rc=EAM_RC, **kw):
+    return oracle.Cell(rho=rho, e=kw.pop("e", 20.0), n_c=n_c, rc=rc, dt=kw.pop("dt", 0.001), potential=1,
+                       eam_c=EAM_C, **kw)
+
+
+def _eam_disordered(n_c=3, rho=4.2, amp=0.06, seed=0):
+    rng = np.random.default_rng(seed)
+    x = oracle.lattice(n_c, rho) + rng.uniform(-amp, amp, size=(4 * n_c ** 3, 3))
+    return x, oracle.box_length(n_c, rho)
+
+
+@pytest.mark.parametrize("n_c,rho,rc", [(3, 4.0, 1.5), (4, 4.6, 1.5), (3, 3.4, 1.45), (4, 5.5, 1.8), (2, 4.0, 1.2)])
+def test_eam_ecold_matches_the_lattice_sum(n_c, rho, rc):
+    cell = _eam_cell(rho, n_c, rc)
+    assert oracle.ecold_cell(cell) / cell.N == pytest.approx(eam_lattice_energy(rho, rc), rel=1e-10)
+
+
+@pytest.mark.parametrize("rho", [3.6, 4.0, 5.0])
+def test_eam_lattice_virial_is_minus_dE_dV(rho):
+    """The T = 0 virial identity W / (3V) = -dE/dV holds for the many-body
+    energy too (it depends on interatomic distances only)."""
+    n_c, rc = 3, EAM_RC
+    N = 4 * n_c ** 3
+    x = oracle.lattice(n_c, rho)
+    L = oracle.box_length(n_c, rho)
+    V = L ** 3
+    W = oracle.forces_eam(x, L, rc, EAM_C)[2]
+    h = 1e-6 * V
+    dEdV = N * (eam_lattice_energy(N / (V + h), rc) - eam_lattice_energy(N / (V - h), rc)) / (2 * h)
+    assert W / (3 * V) == pytest.approx(-dEdV, rel=2e-6)
+
+
+@pytest.mark.parametrize("n_c,rho,rc", [(3, 4.2, 1.5), (2, 4.2, 1.5)], ids=["minimum-image", "multi-image"])
+def test_eam_forces_are_minus_the_energy_gradient(n_c, rho, rc):
+    """Central differences of E_pot: a dropped embedding term (F'_i or F'_j),
+    a wrong sign or a wrong derivative of V or f fails this."""
+    x, L = _eam_disordered(n_c, rho)
+    F, U, W, S, rb = oracle.forces_eam(x, L, rc, EAM_C)
+    rng = np.random.default_rng(1)
+    h = 1e-5
+    scale = np.abs(F).max()
+    for _ in range(12):
+        i, a = int(rng.integers(len(x))), int(rng.integers(3))
+        E = []
+        for s in (h, -h):
+            y = x.copy()
+            y[i, a] += s
+            E.append(oracle.forces_eam(y, L, rc, EAM_C)[1])
+        assert F[i, a] == pytest.approx(-(E[0] - E[1]) / (2 * h), abs=2e-6 * scale)
+
+
+def test_eam_dimer_closed_form():
+    """Two atoms: E = V_s(r) + 2 F(f_s(r)); the force is -dE/dr along the bond."""
+    rc = EAM_RC
+    for r in (0.65, 0.8, 1.1, 1.45):
+        x = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+        F, U, W, S, rb = oracle.forces_eam(x, 20.0, rc, EAM_C)
+        f = float(eam_f(r, rc))
+        assert rb == pytest.approx([f, f], rel=1e-13)
+        assert U == pytest.approx(float(eam_V(r, rc)) - 2 * EAM_C * math.sqrt(f), rel=1e-13)
+        dV = -9.0 * (r ** -10 - rc ** -10)
+        df = -6.0 * (r ** -7 - rc ** -7)
+        dE = dV + 2 * (-EAM_C / (2 * math.sqrt(f))) * df
+        assert F[1, 0] == pytest.approx(-dE, rel=1e-12) and F[0, 0] == pytest.approx(dE, rel=1e-12)
+        assert W == pytest.approx(-dE * r, rel=1e-12)
+
+
+def test_eam_newton3_and_momentum():
+    x, L = _eam_disordered(3, 4.5, seed=3)
+    F = oracle.forces_eam(x, L, EAM_RC, EAM_C)[0]
+    assert np.abs(F.sum(axis=0)).max() < 1e-9 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("a,b", [(0, 0), (1, 2), (2, 0)])
+def test_eam_virial_tensor_is_minus_the_strain_derivative(a, b):
+    """Isolated cluster, affine map x_a -> x_a + e x_b: dE/de = -S_ab."""
+    rng = np.random.default_rng(5)
+    x = oracle.lattice(2, 4.0) + rng.uniform(-0.05, 0.05, size=(32, 3)) + 9.0
+    L = 20.0
+    comp = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}[tuple(sorted((a, b)))]
+    S = oracle.forces_eam(x, L, EAM_RC, EAM_C)[3]
+    h = 1e-6
+    E = []
+    for e in (h, -h):
+        y = x.copy()
+        y[:, a] += e * (x[:, b] - L / 2)
+        E.append(oracle.forces_eam(y, L, EAM_RC, EAM_C)[1])
+    assert S[comp] == pytest.approx(-(E[0] - E[1]) / (2 * h), rel=1e-6, abs=1e-6)
+
+
+def test_eam_nve_energy_error_scales_as_dt_squared():
+    cell = _eam_cell(4.0, 3, e=20.0, seed=2)
+    x, v, Ec = oracle.lift(cell)
+    fl = []
+    for dt, n in ((0.002, 200), (0.001, 400)):
+        c = _eam_cell(4.0, 3, e=20.0, seed=2, dt=dt)
+        r = oracle.run(c, oracle.Schedule(n_steps=n, n_avg=n // 2), x=x, v=v, Ecold_total=Ec)
+        E = r.K + r.U
+        fl.append(np.sqrt(np.mean((E - E.mean()) ** 2)))
+    assert 3.0 < fl[0] / fl[1] < 5.0, fl
+
+
+def test_eam_lift_pins_the_energy_above_cold():
+    """The lifting operator is potential-agnostic: K = N e on the lattice."""
+    cell = _eam_cell(4.4, 3, e=15.0, seed=4)
+    x, v, Ec = oracle.lift(cell)
+    assert Ec == pytest.approx(oracle.ecold_cell(cell), rel=1e-15)
+    assert 0.5 * (v ** 2).sum() == pytest.approx(cell.N * cell.e, rel=1e-6)

@@ -18,8 +18,10 @@ the FP64 oracle timed on this host's cores on a bounded sample, whose results
 are also compared with the GPU's (statistical parity).
 
 Launch shapes are autotuned during the warmup steps (results do not depend
-on them). --workload cfg3 / cfg5 and --precision kahan run the other batch
-workloads and the Kahan accumulation mode with the same accounting.
+on them). --workload cfg3 / cfg5 / eam and --precision kahan run the other
+batch workloads (eam: the embedded-atom form, a many-body potential with a
+density walk and a force walk per step) and the Kahan accumulation mode with
+the same accounting.
 
 Profile summaries (profiles/) are written from rocprofv3 output by
 --trace-summary and --pmc-summary (see each summary for its commands).
@@ -43,9 +45,12 @@ PEAK_FP32 = 157.3          # TFLOP/s, MI355X FP32 vector (packed) spec
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s, 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 FLOP_PAIR = 23             # per ordered in-range pair: force + virial
 FLOP_PAIR_ENERGY = 5       # extra on energy steps
+FLOP_PAIR_EAM = 48         # embedded-atom form: density walk 17 + force and virial walk 31
+FLOP_PAIR_EAM_ENERGY = 7   # extra on energy steps (the pair energy)
 HERE = os.path.dirname(os.path.abspath(__file__))
 ADVANCE = "k_advance"      # the dominant kernel (name prefix in traces)
-PROFILE_NAME = {"cfg2": "uniform_4096x500", "cfg3": "uneven_10000", "cfg5": "large_65536x864"}
+PROFILE_NAME = {"cfg2": "uniform_4096x500", "cfg3": "uneven_10000", "cfg5": "large_65536x864",
+                "eam": "eam_4096x500"}
 
 
 def kernel_sources_sha256() -> str:
@@ -259,9 +264,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg5"], default="cfg2",
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg5", "eam"], default="cfg2",
                     help="cfg2: 4096 x 500 atoms (default); cfg3: 10,000 boxes of 108..4000 atoms; "
-                         "cfg5: 65,536 x 864 atoms at rc 4")
+                         "cfg5: 65,536 x 864 atoms at rc 4; eam: 4096 x 500 atoms of the embedded-atom form")
     ap.add_argument("--precision", choices=["fp64", "kahan"], default="fp64",
                     help="per-atom energy/virial accumulation")
     ap.add_argument("--no-autotune", action="store_true", help="static launch-shape model only")
@@ -308,12 +313,12 @@ def main() -> int:
         torch = None
         sync = lambda: None  # noqa: E731
 
-    w = {"cfg2": wl.cfg2, "cfg3": wl.cfg3, "cfg5": wl.cfg5}[args.workload]()
+    w = {"cfg2": wl.cfg2, "cfg3": wl.cfg3, "cfg5": wl.cfg5, "eam": wl.eam_cu}[args.workload]()
     default = args.workload == "cfg2"
     prec = m.PREC_KAHAN if args.precision == "kahan" else m.PREC_FP64
     specs, sch = m.specs_from_workload(w)
     n = w.n
-    ctx = m.mdeos_create(autotune=0 if args.no_autotune else 1, precision=prec)
+    ctx = m.mdeos_create(autotune=0 if args.no_autotune else 1, precision=prec, potential=w.potential)
     print(f"# workload {w.name}: {n} cells, {int(w.N.sum())} atoms, {w.sched.n_steps} steps, "
           f"precision {args.precision}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -336,7 +341,8 @@ def main() -> int:
 
     # roofline of the advance kernel: algorithmic FLOPs / event-timed duration
     ne = energy_steps(w.sched)
-    flops = float(np.sum(res["pairs"] * (FLOP_PAIR * w.sched.n_steps + FLOP_PAIR_ENERGY * ne)))
+    fp, fpe = (FLOP_PAIR_EAM, FLOP_PAIR_EAM_ENERGY) if w.potential == 1 else (FLOP_PAIR, FLOP_PAIR_ENERGY)
+    flops = float(np.sum(res["pairs"] * (fp * w.sched.n_steps + fpe * ne)))
     k_s = float(np.mean(kernel_ms)) / 1e3
     achieved = flops / k_s / 1e12
     traffic = traffic_from_profile(args.workload, args.precision)
@@ -344,7 +350,7 @@ def main() -> int:
             "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
             "peak_nonpacked": PEAK_FP32_NONPACKED, "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED, 4),
             "kernel_ms": round(float(np.mean(kernel_ms)), 3), "flops_per_launch": flops,
-            "flop_per_pair": FLOP_PAIR, "flop_per_pair_energy_step": FLOP_PAIR + FLOP_PAIR_ENERGY,
+            "flop_per_pair": fp, "flop_per_pair_energy_step": fp + fpe,
             "pairs_per_atom_step": float(np.sum(res["pairs"]) / np.sum(w.N)),
             "state_bytes_per_launch": float(2 * 72 * np.sum(w.N))}
     if traffic is not None:
@@ -360,6 +366,7 @@ def main() -> int:
                    "rho": [round(float(w.rho.min()), 3), round(float(w.rho.max()), 3)],
                    "T": [round(float(w.T.min()), 3), round(float(w.T.max()), 3)],
                    "precision_mode": args.precision, "autotune": not args.no_autotune,
+                   "potential": "eam (Sutton-Chen 9-6 stand-in)" if w.potential == 1 else "ljts",
                    "precision": "fp32 pair forces; fp64 state, energy/virial sums, reductions and re-pin"
                    if args.precision == "fp64" else
                    "fp32 pair forces; Kahan fp32 per-atom energy/virial sums; fp64 state, reductions, re-pin"},

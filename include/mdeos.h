@@ -120,16 +120,35 @@ typedef struct {
 typedef struct {
     int device;                /* HIP device ordinal */
     size_t hbm_budget;         /* bytes of resident cell state the context may hold; 0 = 64 GiB */
-    float skin;                /* Verlet skin; <= 0 selects 0.4 */
+    float skin;                /* Verlet skin; <= 0 selects 0.4 (LJTS) or 0.25 (MDEOS_POT_EAM) */
     int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
     const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
     int precision;             /* how each atom sums its pair energies and virials (forces are FP32):
                                   MDEOS_PREC_FP64 (default) or MDEOS_PREC_KAHAN */
+    int potential;             /* the material of every cell of the context: MDEOS_POT_LJTS (default)
+                                  or MDEOS_POT_EAM */
+    double eam_c;              /* embedding strength c of MDEOS_POT_EAM; <= 0 selects 39.432 */
 } mdeos_config;
 
 /* Per-atom accumulation of pair energy and virial terms. The box sums that
  * follow are FP64 in both modes. */
 enum { MDEOS_PREC_FP64 = 0, MDEOS_PREC_KAHAN = 1 };
+
+/* Interatomic potential, in reduced units with unit atomic mass.
+ * MDEOS_POT_LJTS: Lennard-Jones truncated and shifted at the cell's rc
+ *   (energy eps = 1, length sigma = 1).
+ * MDEOS_POT_EAM: the embedded-atom form of Eq. Etot (appendix),
+ *   E_pot = 1/2 sum_{i != j} V(r_ij) + sum_i F(rhobar_i), rhobar_i = sum_{j != i} f(r_ij),
+ *   with the analytic Sutton-Chen functions V = r^-9, f = r^-6 and
+ *   F = -c sqrt(rhobar) (energy eps = 1, length = the lattice parameter a of
+ *   the fitted crystal; c = 39.432 is the published copper value) standing
+ *   in for the paper's tabulated copper potential. V and f are truncated at
+ *   the cell's rc in shifted-force form, g(r) - g(rc) - (r - rc) g'(rc), so
+ *   forces are continuous there. Densities are atoms per a^3 (4 at the
+ *   fitted lattice). For copper (a = 3.6153 A, eps = 0.012382 eV, 63.546 u)
+ *   the time unit is 2.64 ps, the pressure unit 0.0420 GPa and the
+ *   temperature unit 143.7 K. */
+enum { MDEOS_POT_LJTS = 0, MDEOS_POT_EAM = 1 };
 
 typedef struct mdeos_ctx mdeos_ctx;
 typedef long long mdeos_handle;

@@ -3,7 +3,7 @@
 #include "variants.h"
 
 namespace mdeos {
-#define X(B, A, E, L, W, M, T) MDEOS_DEFINE_VARIANT(B, A, E, L, W, M, T)
+#define X(B, A, E, L, W, M, T, P) MDEOS_DEFINE_VARIANT(B, A, E, L, W, M, T, P)
 MDEOS_VARIANTS_B(X)
 #undef X
 }  // namespace mdeos

@@ -11,7 +11,8 @@
 //   - microscopic model (Sec. II.B): velocity Verlet with a Verlet neighbour
 //     list over an LDS-resident extended box (real atoms + periodic ghost
 //     images), LJTS pair forces in FP32 with per-atom FP32 partials promoted to
-//     FP64 for the energy and virial reductions;
+//     FP64 for the energy and virial reductions; or the embedded-atom form of
+//     Eq. Etot, a density walk then a force walk over the same lists;
 //   - temperature update (Eq. Tcontribution) as an instantaneous energy re-pin
 //     at scheduled steps, in FP64;
 //   - restricting operator (Eq. stress): P = (2K + W) / (3V), T = 2K / N_DOF,
@@ -166,7 +167,7 @@ DEVI double wrap1(double x, double L) {
 // What the pair loop sums per atom besides the force.
 enum { ACC_F = 0, ACC_FW = 1, ACC_FWU = 2, ACC_FWUS = 3 };
 
-template <int BLOCK, int APT, int EXT, bool LLDS, bool MI, bool NVT>
+template <int BLOCK, int APT, int EXT, bool LLDS, bool MI, bool NVT, bool EAM>
 struct Box {
   static constexpr int NW = BLOCK / 64;
   static constexpr int SENT = EXT - 1;  // padding neighbour index
@@ -179,6 +180,7 @@ struct Box {
   PT* px;  // py = px + EXT, pz = px + 2 EXT
   uint16_t* list;  // [list_cap/8][n_pad][8]
   uint16_t *tmp, *sorted;
+  float* fpv;  // F'(rhobar) per position slot (embedded-atom forces; shares tmp/sorted, live outside list builds)
   int *cstart, *cfill, *scanbuf;
   double *ring, *red;
   Ctl* ctl;
@@ -192,6 +194,11 @@ struct Box {
   double invLw;
   double Lw, dt, hdt;
   double V, Ndof, u_shift;
+  // embedded-atom form in shifted-force truncation: f_s(r) = r^-6 + e_c6 r - e_k6,
+  // V_s(r) = r^-9 + e_c9 r - e_k9 (e_c6 = 6 rc^-7, e_k6 = 7 rc^-6, e_c9 = 9 rc^-10,
+  // e_k9 = 10 rc^-9), F(rhobar) = -eam_c sqrt(rhobar)
+  float e_c6, e_k6, e_c9, e_k9;
+  double eam_c;
   double Ecold;  // total cold energy (uniform across the workgroup)
   // the schedule, read once per cell (the step loop writes other fields of
   // the cell record, which would otherwise force these to be re-read)
@@ -229,6 +236,7 @@ struct Box {
     cstart = (int*)(lds + lay.cstart);
     cfill = (int*)(lds + lay.cfill);
     scanbuf = (int*)(lds + lay.tmp);
+    fpv = (float*)(lds + lay.tmp);
     ring = (double*)(lds + lay.ring);
     red = (double*)(lds + lay.red);
     ctl = (Ctl*)(lds + lay.ctl);
@@ -269,6 +277,14 @@ struct Box {
     double irc2 = 1.0 / ((double)c->rc * (double)c->rc);
     double irc6 = irc2 * irc2 * irc2;
     u_shift = 4.0 * (irc6 * irc6 - irc6);
+    if (EAM) {
+      const double rcd = c->rc, irc = 1.0 / rcd;
+      e_c6 = (float)(6.0 * irc6 * irc);
+      e_k6 = (float)(7.0 * irc6);
+      e_c9 = (float)(9.0 * irc6 * irc2 * irc2);
+      e_k9 = (float)(10.0 * irc6 * irc2 * irc);
+      eam_c = p.eam_c;
+    }
     Ecold = c->Ecold;
     n_steps = c->n_steps;
     n_avg = c->n_avg;
@@ -443,6 +459,14 @@ struct Box {
         }
       }
     }
+  }
+
+  // F'(rhobar) of one atom into its ghost slots g .. g + n_images(m) - 1
+  // (the slots write_images fills for the same mask).
+  DEVI void write_image_vals(float v, int m, int g) {
+    const int n = n_images(m);
+#pragma unroll 1
+    for (int i = 0; i < n; ++i) fpv[g + i] = v;
   }
 
   DEVI int cell_coord(float v) const {
@@ -681,9 +705,35 @@ struct Box {
   // ACC_F nothing, ACC_FW the virial, ACC_FWU virial, energy and the in-range
   // pair count. KAHAN sums virial and energy in FP32 with Kahan compensation,
   // otherwise each term is promoted and summed in FP64.
+  // Hands the list blocks of owned atom a (nb blocks of 8 entries, two 16-bit
+  // byte offsets per word) to fn in order.
+  template <class FN>
+  DEVI void walk_list(int a, int nb, FN&& fn) {
+    if (a < n_pad && nb > 0) {
+      // Blocks are loaded one ahead into two alternating registers, so a
+      // block's load latency (device memory when the list does not fit in
+      // LDS) overlaps the arithmetic of the block before it.
+      // The loads are unconditional (the index is clamped to the last
+      // block, nb - 1 < list_cap / 8), so the wait before a block only
+      // covers the load issued before it.
+      // The scheduling barriers keep each load where it is issued (the
+      // scheduler would otherwise sink it next to its use).
+      const uint4* row = reinterpret_cast<const uint4*>(list) + a;
+      uint4 e0 = row[0];
+      for (int b = 0; b < nb; b += 2) {
+        const uint4 e1 = row[min(b + 1, nb - 1) * n_pad];
+        __builtin_amdgcn_sched_barrier(0);
+        fn(e0);
+        if (b + 1 >= nb) break;
+        e0 = row[min(b + 2, nb - 1) * n_pad];
+        __builtin_amdgcn_sched_barrier(0);
+        fn(e1);
+      }
+    }
+  }
+
   template <int ACC, bool KAHAN>
   DEVI void forces_impl() {
-    const uint4* lb = reinterpret_cast<const uint4*>(list);
     const char* pb = reinterpret_cast<const char*>(px);
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
@@ -759,27 +809,7 @@ struct Box {
           }
         }
       };
-      if (a < n_pad && nb > 0) {
-        // Blocks are loaded one ahead into two alternating registers, so a
-        // block's load latency (device memory when the list does not fit in
-        // LDS) overlaps the arithmetic of the block before it.
-        // The loads are unconditional (the index is clamped to the last
-        // block, nb - 1 < list_cap / 8), so the wait before a block only
-        // covers the load issued before it.
-        // The scheduling barriers keep each load where it is issued (the
-        // scheduler would otherwise sink it next to its use).
-        const uint4* row = lb + a;
-        uint4 e0 = row[0];
-        for (int b = 0; b < nb; b += 2) {
-          const uint4 e1 = row[min(b + 1, nb - 1) * n_pad];
-          __builtin_amdgcn_sched_barrier(0);
-          block(e0);
-          if (b + 1 >= nb) break;
-          e0 = row[min(b + 2, nb - 1) * n_pad];
-          __builtin_amdgcn_sched_barrier(0);
-          block(e1);
-        }
-      }
+      walk_list(a, nb, block);
       fx[k] = ax;
       fy[k] = ay;
       fz[k] = az;
@@ -796,12 +826,181 @@ struct Box {
       }
     }
   }
+
+  // --- embedded-atom forces (Eq. Etot, FP32 pair math) --------------------------
+  // First walk: rhobar_i = sum_j f_s(r_ij) over the listed neighbours in range.
+  // Each owner then keeps F'(rhobar_i) = -c / (2 sqrt(rhobar_i)) (0 for an
+  // atom with no neighbour in range, which no pair uses) and 2 F(rhobar_i) in
+  // FP64, and writes F' as float into LDS for the atom and its ghost images.
+  // After a barrier, the second walk forms, with d = x_i - x_j,
+  //   f_ij = -[V_s'(r) + (F'_i + F'_j) f_s'(r)] d / r
+  //        = r^-1 [9 r^-10 - e_c9 + (F'_i + F'_j)(6 r^-7 - e_c6)] d,
+  // the pair virial r.f_ij and, on energy steps, V_s(r). Out-of-range
+  // neighbours and padding take 1/r = 0, so they add exact zeros.
+  DEVI void eam_density(float (&fpi)[APT], double (&emb)[APT]) {
+    const char* pb = reinterpret_cast<const char*>(px);
+    if (t == 0) fpv[SENT] = 0.0f;  // the padding slot's F' must be finite
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      const int a = t + k * BLOCK;
+      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
+      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      float rs = 0.f;
+      auto block = [&](const uint4 ent) __attribute__((always_inline)) {
+        const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
+          const PT* q = reinterpret_cast<const PT*>(pb + off);
+          float dx, dy, dz;
+          if (MI) {
+            dx = (float)mimg(xi64 - q[0]);
+            dy = (float)mimg(yi64 - q[EXT]);
+            dz = (float)mimg(zi64 - q[2 * EXT]);
+          } else {
+            dx = xi - q[0];
+            dy = yi - q[EXT];
+            dz = zi - q[2 * EXT];
+          }
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
+          const float ir = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+          const float ir2 = ir * ir;
+          const float ir6 = ir2 * ir2 * ir2;
+          const float fr = fmaf(e_c6, r2 * ir, ir6 - e_k6);
+          rs += in ? fr : 0.0f;
+        }
+      };
+      walk_list(a, nblk[k], block);
+      const double rb = (double)rs;
+      const double sq = rb > 0.0 ? sqrt(rb) : 0.0;
+      fpi[k] = rb > 0.0 ? (float)(-eam_c / (2.0 * sq)) : 0.0f;
+      emb[k] = -2.0 * eam_c * sq;
+      if (a < N) {
+        fpv[a] = fpi[k];
+        if (!MI && gmask[k]) write_image_vals(fpi[k], gmask[k], gofs[k]);
+      }
+    }
+  }
+
+  template <int ACC, bool KAHAN>
+  DEVI void eam_forces_impl() {
+    float fpi[APT];
+    double emb[APT];
+    eam_density(fpi, emb);
+    __syncthreads();  // every F' of this step is in LDS
+    const char* pb = reinterpret_cast<const char*>(px);
+    const char* fb = reinterpret_cast<const char*>(fpv);
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      const int a = t + k * BLOCK;
+      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
+      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      const float fpk = fpi[k];
+      float ax = 0.f, ay = 0.f, az = 0.f;
+      double wd = 0.0, ud = 0.0;
+      float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;
+      float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
+      int cin = 0;
+      auto block = [&](const uint4 ent) __attribute__((always_inline)) {
+        const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
+          const PT* q = reinterpret_cast<const PT*>(pb + off);
+          // F' of neighbour j: float slot j (the offset is j * sizeof(PT))
+          const float fpj = *reinterpret_cast<const float*>(fb + (MI ? (off >> 1) : off));
+          float dx, dy, dz;
+          if (MI) {
+            dx = (float)mimg(xi64 - q[0]);
+            dy = (float)mimg(yi64 - q[EXT]);
+            dz = (float)mimg(zi64 - q[2 * EXT]);
+          } else {
+            dx = xi - q[0];
+            dy = yi - q[EXT];
+            dz = zi - q[2 * EXT];
+          }
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
+          const float ir = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+          const float ir2 = ir * ir;
+          const float ir6 = ir2 * ir2 * ir2;
+          const float ir7 = ir6 * ir;
+          const float ir10 = ir6 * ir2 * ir2;
+          const float dv = fmaf(9.0f, ir10, -e_c9);
+          const float df = fmaf(6.0f, ir7, -e_c6);
+          const float ff = ir * fmaf(fpk + fpj, df, dv);
+          const float vir = ff * r2;
+          if (ACC == ACC_FWUS) {
+            const float fdx = ff * dx, fdy = ff * dy, fdz = ff * dz;
+            ax += fdx;
+            ay += fdy;
+            az += fdz;
+            sxx = fmaf(fdx, dx, sxx);
+            syy = fmaf(fdy, dy, syy);
+            szz = fmaf(fdz, dz, szz);
+            sxy = fmaf(fdx, dy, sxy);
+            sxz = fmaf(fdx, dz, sxz);
+            syz = fmaf(fdy, dz, syz);
+          } else {
+            ax = fmaf(ff, dx, ax);
+            ay = fmaf(ff, dy, ay);
+            az = fmaf(ff, dz, az);
+          }
+          if (ACC >= ACC_FW) {
+            if (KAHAN) {
+              const float y1 = vir - wc, t1 = ws + y1;
+              wc = (t1 - ws) - y1;
+              ws = t1;
+            } else {
+              wd += (double)vir;
+            }
+          }
+          if (ACC >= ACC_FWU) {
+            const float e = in ? fmaf(e_c9, r2 * ir, ir6 * ir2 * ir - e_k9) : 0.0f;
+            if (KAHAN) {
+              const float y2 = e - uc, t2 = us + y2;
+              uc = (t2 - us) - y2;
+              us = t2;
+            } else {
+              ud += (double)e;
+            }
+            cin += in ? 1 : 0;
+          }
+        }
+      };
+      walk_list(a, nblk[k], block);
+      fx[k] = ax;
+      fy[k] = ay;
+      fz[k] = az;
+      if (KAHAN) {
+        wd = (double)ws - (double)wc;
+        ud = (double)us - (double)uc;
+      }
+      wi[k] = ACC >= ACC_FW ? wd : 0.0;
+      // halved with the pair terms: 1/2 sum_j V_s + F(rhobar_i)
+      ui[k] = ACC >= ACC_FWU ? ud + emb[k] : 0.0;
+      cnt_in[k] = (ACC >= ACC_FWU && a < N) ? cin : 0;
+      if (ACC == ACC_FWUS) {
+        sv[0][k] = sxx; sv[1][k] = syy; sv[2][k] = szz;
+        sv[3][k] = sxy; sv[4][k] = sxz; sv[5][k] = syz;
+      }
+    }
+  }
+
   template <int ACC>
   DEVI void forces() {
-    if (kahan)
-      forces_impl<ACC, true>();
-    else
-      forces_impl<ACC, false>();
+    if (EAM) {
+      if (kahan)
+        eam_forces_impl<ACC, true>();
+      else
+        eam_forces_impl<ACC, false>();
+    } else {
+      if (kahan)
+        forces_impl<ACC, true>();
+      else
+        forces_impl<ACC, false>();
+    }
   }
 
   // --- per-step bookkeeping (FP64) --------------------------------------------------
@@ -1413,10 +1612,10 @@ struct Box {
   }
 };
 
-template <int BLOCK, int APT, int EXT, bool LLDS, int WPE, bool MI, bool NVT>
+template <int BLOCK, int APT, int EXT, bool LLDS, int WPE, bool MI, bool NVT, bool EAM>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_advance(AdvanceParams p) {
   extern __shared__ __align__(16) unsigned char lds[];
-  Box<BLOCK, APT, EXT, LLDS, MI, NVT> box(p, lds);
+  Box<BLOCK, APT, EXT, LLDS, MI, NVT, EAM> box(p, lds);
   if (threadIdx.x == 0) {
     box.PX(EXT - 1) = kSentinelPos;
     box.PY(EXT - 1) = kSentinelPos;
@@ -1438,24 +1637,25 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
 }  // namespace
 
 // Host-side wrappers of one launch shape, defined in the variant translation units.
-#define MDEOS_DEFINE_VARIANT(B, A, E, L, W, M, T)                                                               \
-  namespace variants {                                                                                        \
-  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M##_##T(const AdvanceParams& p, int grid, int lds,           \
-                                                            hipStream_t s) {                                  \
-    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W, M != 0, T != 0>), dim3(grid), dim3(B), lds, s, p);         \
-    return hipGetLastError();                                                                                 \
-  }                                                                                                           \
-  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M##_##T() {                                                  \
-    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W, M != 0, T != 0>,                       \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                          \
-  }                                                                                                           \
-  int occ_##B##_##A##_##E##_##L##_##W##_##M##_##T(int lds) {                                                   \
-    int n = 0;                                                                                                \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_advance<B, A, E, L != 0, W, M != 0, T != 0>, \
-                                                     B, lds) != hipSuccess)                                   \
-      n = 1;                                                                                                  \
-    return n;                                                                                                 \
-  }                                                                                                           \
+#define MDEOS_DEFINE_VARIANT(B, A, E, L, W, M, T, P)                                                      \
+  namespace variants {                                                                                     \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P(const AdvanceParams& p, int grid, int lds,  \
+                                                                  hipStream_t s) {                         \
+    hipLaunchKernelGGL((k_advance<B, A, E, L != 0, W, M != 0, T != 0, P != 0>), dim3(grid), dim3(B), lds, s, \
+                       p);                                                                                 \
+    return hipGetLastError();                                                                              \
+  }                                                                                                        \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P() {                                          \
+    return hipFuncSetAttribute((const void*)k_advance<B, A, E, L != 0, W, M != 0, T != 0, P != 0>,          \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);                       \
+  }                                                                                                        \
+  int occ_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P(int lds) {                                           \
+    int n = 0;                                                                                             \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                      \
+            &n, (const void*)k_advance<B, A, E, L != 0, W, M != 0, T != 0, P != 0>, B, lds) != hipSuccess)  \
+      n = 1;                                                                                               \
+    return n;                                                                                              \
+  }                                                                                                        \
   }
 
 }  // namespace mdeos

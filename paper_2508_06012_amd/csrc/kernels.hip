@@ -7,11 +7,11 @@
 namespace mdeos {
 
 namespace variants {
-#define X(B, A, E, L, W, M, T)                                                                       \
-  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M##_##T(const AdvanceParams& p, int grid, int lds,  \
-                                                            hipStream_t s);                            \
-  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M##_##T();                                           \
-  int occ_##B##_##A##_##E##_##L##_##W##_##M##_##T(int lds);
+#define X(B, A, E, L, W, M, T, P)                                                                          \
+  hipError_t launch_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P(const AdvanceParams& p, int grid, int lds,  \
+                                                                  hipStream_t s);                            \
+  hipError_t attr_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P();                                           \
+  int occ_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P(int lds);
 MDEOS_VARIANTS(X)
 #undef X
 }  // namespace variants
@@ -73,7 +73,7 @@ __global__ void k_zero_ints(int* p, int n) {
 }  // namespace
 
 static const Variant kVariants[] = {
-#define X(B, A, E, L, W, M, T) {B, A, E, L, W, M, T},
+#define X(B, A, E, L, W, M, T, P) {B, A, E, L, W, M, T, P},
     MDEOS_VARIANTS(X)
 #undef X
 };
@@ -88,9 +88,10 @@ bool variant_available(const Variant& v) {
 }
 
 hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, int lds_bytes, hipStream_t s) {
-#define X(B, A, E, L, W, M, T)                                                                                  \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M && v.nvt == T) \
-    return variants::launch_##B##_##A##_##E##_##L##_##W##_##M##_##T(p, grid, lds_bytes, s);
+#define X(B, A, E, L, W, M, T, P)                                                                  \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M && v.nvt == T && \
+      v.eam == P)                                                                                           \
+    return variants::launch_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P(p, grid, lds_bytes, s);
   MDEOS_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -98,17 +99,18 @@ hipError_t launch_advance(const Variant& v, const AdvanceParams& p, int grid, in
 
 hipError_t init_kernel_attributes() {
   hipError_t e = hipSuccess;
-#define X(B, A, E, L, W, M, T) \
-  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W##_##M##_##T();
+#define X(B, A, E, L, W, M, T, P) \
+  if (e == hipSuccess) e = variants::attr_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P();
   MDEOS_VARIANTS(X)
 #undef X
   return e;
 }
 
 int occupancy(const Variant& v, int lds_bytes) {
-#define X(B, A, E, L, W, M, T)                                                                                  \
-  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M && v.nvt == T) \
-    return variants::occ_##B##_##A##_##E##_##L##_##W##_##M##_##T(lds_bytes);
+#define X(B, A, E, L, W, M, T, P)                                                                  \
+  if (v.block == B && v.apt == A && v.ext == E && v.list_lds == L && v.wpe == W && v.mi == M && v.nvt == T && \
+      v.eam == P)                                                                                           \
+    return variants::occ_##B##_##A##_##E##_##L##_##W##_##M##_##T##_##P(lds_bytes);
   MDEOS_VARIANTS(X)
 #undef X
   return 1;

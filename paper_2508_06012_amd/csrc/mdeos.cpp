@@ -279,7 +279,18 @@ void RangeAlloc::release_raw(int off, int n) {
 
 mdeos_status Ctx::init(const mdeos_config* cfg) {
   device = cfg ? cfg->device : 0;
-  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : 0.4f;
+  potential = cfg ? cfg->potential : MDEOS_POT_LJTS;
+  if (potential != MDEOS_POT_LJTS && potential != MDEOS_POT_EAM) {
+    set_error("potential must be MDEOS_POT_LJTS or MDEOS_POT_EAM");
+    return MDEOS_INVALID_ARG;
+  }
+  const double c_in = cfg ? cfg->eam_c : 0.0;
+  if (!std::isfinite(c_in)) {
+    set_error("eam_c must be finite");
+    return MDEOS_INVALID_ARG;
+  }
+  eam_c = c_in > 0.0 ? c_in : 39.432;
+  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : (potential == MDEOS_POT_EAM ? 0.25f : 0.4f);
   hbm_budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : (size_t)64 << 30;
   autotune = cfg ? cfg->autotune : 0;
   if (cfg && cfg->tune_cache) tune_cache = cfg->tune_cache;
@@ -314,8 +325,9 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   load_tune_cache();
   if (const char* fv = getenv("MDEOS_FORCE_VARIANT")) {
     Variant v{};
-    const int nf = sscanf(fv, "%d,%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi, &v.nvt);
-    if ((nf == 6 || nf == 7) && variant_available(v))
+    const int nf = sscanf(fv, "%d,%d,%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi,
+                          &v.nvt, &v.eam);
+    if (nf >= 6 && variant_available(v))
       forced_variant = v;
   }
   return MDEOS_OK;
@@ -605,7 +617,8 @@ int Ctx::rank_variants(const CellPlan& p, std::vector<Variant>& out) const {
   for (int i = 0; i < variant_count(); ++i) {
     const Variant v = variant_at(i);
     const int lds = lds_layout(v.ext, c, v.list_lds, v.mi).total;
-    if (v.mi != p.minimg || v.nvt != p.nvt || v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax)
+    if (v.mi != p.minimg || v.nvt != p.nvt || v.eam != (potential == MDEOS_POT_EAM ? 1 : 0) ||
+        v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax)
       continue;
     const int wg_by_lds = kLdsMax / lds, wg_by_regs = std::max(1, 4 * v.wpe / (v.block / 64));
     const int waves = std::min(wg_by_lds, wg_by_regs) * (v.block / 64);
@@ -702,8 +715,10 @@ std::string Ctx::tune_key(const CellPlan& p) const {
   char buf[128];
   snprintf(buf, sizeof(buf), "%s/N%d/rl%.2f/ext%d/list%d/cells%d/mi%d/prec%d", arch.c_str(), p.N, p.rl,
            align_up(p.ext_need, 512), align_up(p.list_cap, 16), align_up(p.ncell, 256), p.minimg, precision);
-  if (p.nvt) return std::string(buf) + "/nvt";
-  return buf;
+  std::string key = buf;
+  if (p.nvt) key += "/nvt";
+  if (potential == MDEOS_POT_EAM) key += "/eam";
+  return key;
 }
 
 // Merged plan of a set of cells with one atom count: capacities are maxima.
@@ -808,8 +823,8 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
   std::string key = hdr;
   for (Bucket& b : buckets) {
     char bb[128];
-    snprintf(bb, sizeof(bb), "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%zu;", b.v.mi, b.v.nvt, b.v.block, b.v.apt, b.v.ext, b.v.list_lds,
-             b.caps.list_cap, b.caps.ncell_cap, b.caps.n_pad, b.grid, b.lds, b.gl_off);
+    snprintf(bb, sizeof(bb), "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%zu;", b.v.mi, b.v.nvt, b.v.eam, b.v.block, b.v.apt,
+             b.v.ext, b.v.list_lds, b.v.wpe, b.caps.list_cap, b.caps.ncell_cap, b.caps.n_pad, b.grid, b.lds, b.gl_off);
     key += bb;
   }
   HCHECK(hipMemcpyAsync(d_work, host_work.data(), sizeof(int) * host_work.size(), hipMemcpyHostToDevice, s));
@@ -904,6 +919,7 @@ AdvanceParams Ctx::make_params(const Bucket& b, int bi, int step_budget) {
   p.gl_list = b.v.list_lds ? nullptr : d_gl + b.gl_off / 2;
   p.caps = b.caps;
   p.kahan = precision == MDEOS_PREC_KAHAN ? 1 : 0;
+  p.eam_c = eam_c;
   return p;
 }
 

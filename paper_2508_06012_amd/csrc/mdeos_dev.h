@@ -109,6 +109,7 @@ struct AdvanceParams {
   uint16_t* gl_list;    // device-memory neighbour lists (per workgroup), or null
   Caps caps;
   int kahan;            // 1: Kahan-compensated FP32 per-atom energy/virial sums, 0: FP64
+  double eam_c;         // embedding strength of the embedded-atom variants
 };
 
 // LDS layout of one box. EXT is the stride of each position array (compile
@@ -119,7 +120,8 @@ struct AdvanceParams {
 struct LdsLayout {
   int pos;        // float[3][EXT] (double[3][EXT] for minimum image)
   int list;       // uint16[list_cap/8][n_pad][8] (when the list lives in LDS)
-  int tmp;        // uint16[EXT]   (the ghost-count scan uses tmp..sorted as int[N])
+  int tmp;        // uint16[EXT]   (the ghost-count scan uses tmp..sorted as int[N]; outside the
+                  //                list build the embedded-atom forces keep F'(rhobar) there as float[EXT])
   int sorted;     // uint16[EXT]
   int cstart;     // int[ncell_cap + 1]
   int cfill;      // int[ncell_cap]
@@ -153,13 +155,14 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
 // Kernel variants the library is built with (template arguments of the
 // advance kernel): threads per box, atoms per thread, position stride, where
 // the neighbour list lives, the waves per SIMD the registers must allow, and
-// minimum image (no ghosts) for large boxes.
+// minimum image (no ghosts) for large boxes, Langevin integration, and the
+// embedded-atom potential instead of LJTS.
 struct Variant {
-  int block, apt, ext, list_lds, wpe, mi, nvt;
+  int block, apt, ext, list_lds, wpe, mi, nvt, eam;
 };
 inline bool same_variant(const Variant& a, const Variant& b) {
   return a.block == b.block && a.apt == b.apt && a.ext == b.ext && a.list_lds == b.list_lds && a.wpe == b.wpe &&
-         a.mi == b.mi && a.nvt == b.nvt;
+         a.mi == b.mi && a.nvt == b.nvt && a.eam == b.eam;
 }
 
 // Host entry points implemented in kernels.hip.

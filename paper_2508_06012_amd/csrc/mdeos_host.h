@@ -110,6 +110,8 @@ struct Ctx {
   int autotune = 0;
   int tune_runs = 0;  // buckets timed by the autotuner so far
   int precision = MDEOS_PREC_FP64;
+  int potential = MDEOS_POT_LJTS;  // material of every cell of the context
+  double eam_c = 39.432;           // embedding strength of MDEOS_POT_EAM
   std::string arch = "gfx950";  // device architecture (tune-cache key)
   std::string tune_cache;
   std::recursive_mutex mu;

@@ -48,9 +48,9 @@ void Ctx::load_tune_cache() {
     size_t lb = s.find('[', j), rb = s.find(']', j);
     if (lb == std::string::npos || rb == std::string::npos) break;
     Variant v{};
-    const int nf = sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d , %d , %d", &v.block, &v.apt, &v.ext,
-                          &v.list_lds, &v.wpe, &v.mi, &v.nvt);
-    if ((nf == 6 || nf == 7) && variant_available(v))
+    const int nf = sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d , %d , %d , %d", &v.block, &v.apt, &v.ext,
+                          &v.list_lds, &v.wpe, &v.mi, &v.nvt, &v.eam);
+    if (nf >= 6 && variant_available(v))
       tuned[key] = v;
     i = rb + 1;
   }
@@ -66,7 +66,8 @@ void Ctx::save_tune_cache() {
     size_t k = 0;
     for (auto& kv : tuned) {
       f << "  \"" << kv.first << "\": [" << kv.second.block << ", " << kv.second.apt << ", " << kv.second.ext << ", "
-        << kv.second.list_lds << ", " << kv.second.wpe << ", " << kv.second.mi << ", " << kv.second.nvt << "]"
+        << kv.second.list_lds << ", " << kv.second.wpe << ", " << kv.second.mi << ", " << kv.second.nvt << ", "
+        << kv.second.eam << "]"
         << (++k < tuned.size() ? "," : "") << "\n";
     }
     f << "}\n";

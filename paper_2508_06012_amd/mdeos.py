@@ -21,6 +21,7 @@ OK, INVALID_ARG, OUT_OF_MEMORY, DEVICE_ERROR, NOT_READY, ADMISSION_FULL, NO_DEVI
 CELL_NONFINITE, CELL_ENERGY_BELOW_COLD, CELL_DRIFT, CELL_OVERFLOW, CELL_COLD_RELIFT = 1, 2, 4, 8, 16
 PREC_FP64, PREC_KAHAN = 0, 1
 NVE_REPIN, NVT_LANGEVIN = 0, 1
+POT_LJTS, POT_EAM = 0, 1
 MAX_RESCALE = 8
 
 
@@ -45,7 +46,7 @@ class Result(C.Structure):
 class Config(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget", C.c_size_t), ("skin", C.c_float), ("autotune", C.c_int),
                 ("tune_cache", C.c_char_p),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("potential", C.c_int), ("eam_c", C.c_double)]
 
 
 class PlanInfo(C.Structure):
@@ -231,8 +232,10 @@ def mdeos_cell_bytes(n_c: int) -> int:
 
 
 def mdeos_create(device: int = 0, hbm_budget: int = 0, skin: float = 0.0, autotune: int = 0,
-                 tune_cache: str | None = None, precision: int = 0) -> C.c_void_p:
-    cfg = Config(device, hbm_budget, skin, autotune, tune_cache.encode() if tune_cache else None, precision)
+                 tune_cache: str | None = None, precision: int = 0, potential: int = 0,
+                 eam_c: float = 0.0) -> C.c_void_p:
+    cfg = Config(device, hbm_budget, skin, autotune, tune_cache.encode() if tune_cache else None, precision,
+                 potential, eam_c)
     ctx = C.c_void_p()
     _check(lib().mdeos_create(C.byref(cfg), C.byref(ctx)), "mdeos_create")
     return ctx

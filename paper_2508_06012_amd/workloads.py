@@ -62,6 +62,7 @@ class Workload:
     sched: Schedule
     T: np.ndarray = None
     meta: dict = field(default_factory=dict)
+    potential: int = 0  # 0: LJTS; 1: the embedded-atom form (Sutton-Chen (9, 6) stand-in)
 
     @property
     def n(self) -> int:
@@ -79,6 +80,7 @@ class Workload:
         return Workload(
             self.name + "[sub]", self.rho[idx], self.e[idx], self.n_c[idx], self.rc[idx], self.dt[idx],
             self.seed, self.cell_id[idx], self.sched, None if self.T is None else self.T[idx], dict(self.meta),
+            self.potential,
         )
 
 
@@ -170,6 +172,25 @@ def cfg5(seed: int = DEFAULT_SEED, n: int = 65_536) -> Workload:
     return Workload(
         f"cfg5-large-{n}x864", rho, e_from_T(T, N), np.full(n, 6), np.full(n, 4.0), np.full(n, 0.002), seed,
         np.arange(n), Schedule(1000, 500, (250, 500)), T,
+    )
+
+
+def eam_cu(seed: int = DEFAULT_SEED, mesh: int = 64) -> Workload:
+    """Many-body batch: the embedded-atom form with the Sutton-Chen (9, 6)
+    functions standing in for the paper's copper potential (App. A). A 64 x 64
+    mesh of 500-atom boxes, rho ~ [4.0, 6.0] atoms per a^3 from a smooth field
+    (the fitted lattice up to 1.5x compression, about 150 GPa in copper units),
+    T ~ U[7, 35] (about 1000-5000 K), rc = 1.5 a, dt = 0.001 (2.6 fs), 2000
+    steps, re-pins at 500 and 1000, average over the last 1000."""
+    rng = np.random.default_rng(seed + 7)
+    f, modes = smooth_field(mesh, rng)
+    rho = 4.0 + 2.0 * f.ravel()
+    n = rho.size
+    T = rng.uniform(7.0, 35.0, size=n)
+    N = np.full(n, 500)
+    return Workload(
+        f"eam-cu-{n}x500", rho, e_from_T(T, N), np.full(n, 5), np.full(n, 1.5), np.full(n, 0.001), seed,
+        np.arange(n), Schedule(2000, 1000, (500, 1000)), T, {"modes": modes}, potential=1,
     )
 
 

@@ -96,6 +96,29 @@ def test_create_rejects_unknown_precision():
     assert "precision" in str(e.value)
 
 
+@pytest.mark.parametrize("kw,what", [({"potential": 2}, "potential"), ({"potential": 1, "eam_c": float("nan")},
+                                                                        "eam_c")])
+def test_create_rejects_an_unknown_potential(kw, what):
+    # checked before any device call, so this runs on the CPU too
+    with pytest.raises(m.MdeosError) as e:
+        m.mdeos_create(**kw)
+    assert e.value.status == m.INVALID_ARG
+    assert what in str(e.value)
+
+
+def test_eam_workload_cells_plan_into_eam_shapes():
+    """Every cell of the embedded-atom bench workload plans (at the EAM default
+    skin) with at most 4095 position slots, which the 4096-stride embedded-atom
+    shapes for 500-atom boxes hold (a shape serves any plan it covers)."""
+    from paper_2508_06012_amd import workloads as wl
+    w = wl.eam_cu()
+    assert w.potential == 1 and w.n == 4096 and set(w.N) == {500}
+    assert 4.0 <= w.rho.min() and w.rho.max() <= 6.0
+    specs, _ = m.specs_from_workload(w.subset(np.arange(0, 4096, 64)))
+    caps = [m.mdeos_plan(s, 0.25).ext_cap for s in specs]
+    assert max(caps) < 4096, max(caps)
+
+
 def test_config_layout_matches_header():
     """The binding's config struct lists the header's fields in order."""
     import re

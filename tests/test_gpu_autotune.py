@@ -30,7 +30,7 @@ def test_autotune_writes_cache_and_keeps_bits(tmp_path):
     with open(cache) as f:
         entries = json.load(f)
     print("tune cache:", entries, flush=True)
-    assert entries and all("/prec0" in k and len(v) == 7 for k, v in entries.items())
+    assert entries and all("/prec0" in k and len(v) == 8 for k, v in entries.items())
 
     ctx = m.mdeos_create()
     try:

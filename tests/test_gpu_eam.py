@@ -1,0 +1,167 @@
+"""The embedded-atom form (Eq. Etot, the Sutton-Chen (9, 6) stand-in in
+shifted-force truncation) on the GPU, through the C ABI, against the FP64
+oracle.
+
+The bars are those of the LJTS path:
+  - forces, norm-wise per step: ||F_gpu - F_orc|| / ||F_orc|| <= 1e-5
+  - E_pot and E_tot per step: |dE| / max(|E_pot|, K) <= 1e-6; W per step to
+    1e-5 of max(|W|, |E_pot|) (it carries the force rounding)
+Covered: ghost-image boxes (lists in LDS and in device memory), a box whose
+cutoff exceeds half its edge (several images of one atom in range), a larger
+cutoff, and a minimum-image box of 4000 atoms; the lift; 50 free-running
+steps with an energy re-pin; bitwise alone vs batch vs chunked; a context
+of each potential side by side. Replica ensembles of two states are in
+test_gpu_ensembles.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06012_amd import mdeos as m
+from paper_2508_06012_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-5
+E_TOL = 1e-6
+W_TOL = 1e-5
+C_SC = 39.432
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = m.mdeos_create(potential=m.POT_EAM)
+    yield c
+    m.mdeos_destroy(c)
+
+
+def gspec(cell: oracle.Cell):
+    return m.make_specs(cell.rho, cell.e, cell.n_c, cell.rc, cell.dt, cell.seed, cell.cell_id)[0]
+
+
+def relnorm(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def ecell(rho, T, n_c, rc=1.5, cell_id=1):
+    return oracle.Cell(rho=rho, e=wl.e_from_T(T, 4 * n_c ** 3).item(), n_c=n_c, rc=rc, dt=0.001, seed=7,
+                       cell_id=cell_id, potential=1, eam_c=C_SC)
+
+
+CELLS = [ecell(4.4, 14.0, 4, cell_id=1), ecell(5.5, 30.0, 5, cell_id=2), ecell(4.4, 10.0, 3, cell_id=3),
+         ecell(3.6, 7.0, 6, rc=1.8, cell_id=4)]
+IDS = ["eam-256", "eam-500-hot", "eam-multi-image-108", "eam-rc1.8-864"]
+
+
+@pytest.mark.parametrize("cell", CELLS, ids=IDS)
+def test_forces_on_oracle_positions(ctx, cell):
+    r = oracle.run(cell, oracle.Schedule(n_steps=60, n_avg=20, n_blocks=2, rescale_steps=(20,)))
+    L = oracle.box_length(cell.n_c, cell.rho)
+    x = r.x.astype(np.float32).astype(np.float64)
+    F0, U0, W0, _, _ = oracle.forces_eam(x, L, cell.rc, C_SC)
+    print(f"eam debug_forces {cell}", flush=True)
+    F, U, W = m.mdeos_debug_forces(ctx, gspec(cell), x)
+    print(f"  rel F {relnorm(F, F0):.2e} U {abs(U - U0) / abs(U0):.2e} W {abs(W - W0) / max(abs(W0), abs(U0)):.2e}",
+          flush=True)
+    assert relnorm(F, F0) <= F_TOL
+    assert abs(U - U0) <= E_TOL * abs(U0)
+    assert abs(W - W0) <= W_TOL * max(abs(W0), abs(U0))
+
+
+def test_forces_minimum_image_4000(ctx):
+    """A box too large for ghost images in LDS: the minimum-image variant."""
+    cell = ecell(4.0, 20.0, 10, cell_id=5)
+    plan = m.mdeos_plan(gspec(cell), 0.25)
+    assert plan.ext_cap == 4087  # the minimum-image plan: real atoms only
+    rng = np.random.default_rng(3)
+    L = oracle.box_length(cell.n_c, cell.rho)
+    x = (oracle.lattice(cell.n_c, cell.rho) + rng.uniform(-0.08, 0.08, size=(cell.N, 3))) % L
+    x = x.astype(np.float32).astype(np.float64)
+    F0, U0, W0, _, _ = oracle.forces_eam(x, L, cell.rc, C_SC)
+    print(f"eam debug_forces minimum image {cell}", flush=True)
+    F, U, W = m.mdeos_debug_forces(ctx, gspec(cell), x)
+    print(f"  rel F {relnorm(F, F0):.2e} U {abs(U - U0) / abs(U0):.2e}", flush=True)
+    assert relnorm(F, F0) <= F_TOL
+    assert abs(U - U0) <= E_TOL * abs(U0)
+    assert abs(W - W0) <= W_TOL * max(abs(W0), abs(U0))
+
+
+@pytest.mark.parametrize("cell", CELLS, ids=IDS)
+def test_lift_matches_oracle(ctx, cell):
+    sch = m.make_schedule(10, 10, (), 2)
+    x0, v0, Ec = oracle.lift(cell)
+    print(f"eam lift {cell}", flush=True)
+    h = m.mdeos_lift(ctx, [gspec(cell)], sch)[0]
+    xyz, v, step = m.mdeos_state_export(ctx, h, cell.N)
+    m.mdeos_advance(ctx, [h], 10 ** 6)
+    r = m.mdeos_restrict(ctx, [h])[0]
+    m.mdeos_release(ctx, [h])
+    assert step == 0
+    assert np.array_equal(xyz, x0)
+    assert np.abs(v - v0).max() <= 2.4e-7 * np.abs(v0).max()
+    assert r["Ecold"] * cell.N == pytest.approx(Ec, rel=E_TOL)
+
+
+@pytest.mark.parametrize("cell", CELLS[:3], ids=IDS[:3])
+def test_first_50_steps(ctx, cell):
+    n = 50
+    x0, v0, Ec = oracle.lift(cell)
+    ref = oracle.run(cell, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(20,), energy_every=5),
+                     x=x0, v=v0, Ecold_total=Ec, n_recF=n + 1)
+    sch = m.make_schedule(200, 100, (20,), 10, 5)
+    print(f"eam trajectory {cell}", flush=True)
+    h = m.mdeos_lift_from_state(ctx, gspec(cell), sch, x0, v0)
+    F, K, U, W = m.mdeos_debug_trajectory(ctx, h, n, cell.N)
+    m.mdeos_release(ctx, [h])
+    fn = np.array([np.linalg.norm(ref.F[k]) for k in range(n + 1)])
+    ferr = np.array([np.linalg.norm(F[k] - ref.F[k]) / max(fn[k], fn[-1]) for k in range(n + 1)])
+    den = np.maximum(np.abs(ref.U), ref.K)
+    uerr, kerr = np.abs(U - ref.U) / den, np.abs(K - ref.K) / den
+    eerr = np.abs((K + U) - (ref.K + ref.U)) / den
+    werr = np.abs(W - ref.W) / np.maximum(np.abs(ref.W), np.abs(ref.U))
+    print(f"  max rel err: F {ferr.max():.2e} U {uerr.max():.2e} K {kerr.max():.2e} E {eerr.max():.2e} "
+          f"W {werr.max():.2e}", flush=True)
+    assert ferr.max() <= F_TOL, (ferr.argmax(), ferr.max())
+    assert uerr.max() <= E_TOL and kerr.max() <= E_TOL and eerr.max() <= E_TOL
+    assert werr.max() <= W_TOL
+
+
+def test_alone_batch_and_chunked_are_bitwise_equal(ctx):
+    w = wl.eam_cu().subset(np.arange(0, 4096, 128))
+    specs, sch = m.specs_from_workload(w)
+    sch = m.make_schedule(400, 200, (100, 200))
+    print(f"eam batch of {w.n}", flush=True)
+    batch = m.mdeos_eval_batch(ctx, specs, sch)
+    assert not (batch["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)).any()
+    for i in (0, 17, w.n - 1):
+        alone = m.mdeos_eval_batch(ctx, (m.CellSpec * 1)(specs[i]), sch)[0]
+        assert alone.tobytes() == batch[i].tobytes(), i
+    h = m.mdeos_lift(ctx, specs, sch)
+    for k in (1, 9, 50, 77, 1000):
+        m.mdeos_advance(ctx, h, k)
+    chunked = m.mdeos_restrict(ctx, h)
+    m.mdeos_release(ctx, h)
+    assert chunked.tobytes() == batch.tobytes()
+    assert batch["Ecold"].max() < -100.0  # cohesive energies of the many-body crystal
+
+
+def test_each_context_runs_its_own_potential(ctx):
+    """One spec valid for both materials (a dilute state in either unit
+    system), evaluated by an LJTS and an embedded-atom context side by side:
+    each E_cold is its own potential's, as the oracle computes it."""
+    kw = dict(rho=1.0, e=1.5, n_c=4, rc=1.5, dt=0.001, seed=3, cell_id=0)
+    sch = m.make_schedule(20, 10, (), 2)
+    spec = m.make_specs(kw["rho"], kw["e"], kw["n_c"], kw["rc"], kw["dt"], kw["seed"], kw["cell_id"])
+    lj = m.mdeos_create()
+    try:
+        r_lj = m.mdeos_eval_batch(lj, spec, sch)[0]
+    finally:
+        m.mdeos_destroy(lj)
+    r_eam = m.mdeos_eval_batch(ctx, spec, sch)[0]
+    N = 4 * kw["n_c"] ** 3
+    e_lj = oracle.ecold_cell(oracle.Cell(**kw)) / N
+    e_eam = oracle.ecold_cell(oracle.Cell(**kw, potential=1, eam_c=C_SC)) / N
+    print(f"E_cold/N: LJTS {r_lj['Ecold']:.6f} (oracle {e_lj:.6f}), EAM {r_eam['Ecold']:.6f} (oracle {e_eam:.6f})",
+          flush=True)
+    assert r_lj["Ecold"] == pytest.approx(e_lj, rel=E_TOL)
+    assert r_eam["Ecold"] == pytest.approx(e_eam, rel=E_TOL)

@@ -36,7 +36,7 @@ def test_replica_mean_matches_oracle(name, prec):
     s = STATES[name]
     M = s["M"]
     print(f"replicas {name} M {M} precision {prec}", flush=True)
-    ctx = m.mdeos_create(precision=prec)
+    ctx = m.mdeos_create(precision=prec, potential=s.get("potential", 0))
     try:
         specs = m.make_specs(np.full(M, s["rho"]), np.full(M, s["e"]), s["n_c"], s["rc"], s["dt"],
                              np.arange(s["seed0"], s["seed0"] + M), s["cell_id"])

@@ -290,7 +290,7 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     return MDEOS_INVALID_ARG;
   }
   eam_c = c_in > 0.0 ? c_in : 39.432;
-  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : (potential == MDEOS_POT_EAM ? 0.25f : 0.4f);
+  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : (potential == MDEOS_POT_EAM ? 0.15f : 0.4f);
   hbm_budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : (size_t)64 << 30;
   autotune = cfg ? cfg->autotune : 0;
   if (cfg && cfg->tune_cache) tune_cache = cfg->tune_cache;

@@ -10,8 +10,9 @@ Covered: ghost-image boxes (lists in LDS and in device memory), a box whose
 cutoff exceeds half its edge (several images of one atom in range), a larger
 cutoff, and a minimum-image box of 4000 atoms; the lift; 50 free-running
 steps with an energy re-pin; bitwise alone vs batch vs chunked; a context
-of each potential side by side. Replica ensembles of two states are in
-test_gpu_ensembles.py.
+of each potential side by side; the Langevin shapes (50 GJF steps with a
+temperature update, per step, and batch vs alone). Replica ensembles of two
+states are in test_gpu_ensembles.py.
 """
 import numpy as np
 import pytest
@@ -71,7 +72,7 @@ def test_forces_on_oracle_positions(ctx, cell):
 def test_forces_minimum_image_4000(ctx):
     """A box too large for ghost images in LDS: the minimum-image variant."""
     cell = ecell(4.0, 20.0, 10, cell_id=5)
-    plan = m.mdeos_plan(gspec(cell), 0.25)
+    plan = m.mdeos_plan(gspec(cell), 0.15)
     assert plan.ext_cap == 4087  # the minimum-image plan: real atoms only
     rng = np.random.default_rng(3)
     L = oracle.box_length(cell.n_c, cell.rho)
@@ -165,3 +166,39 @@ def test_each_context_runs_its_own_potential(ctx):
           flush=True)
     assert r_lj["Ecold"] == pytest.approx(e_lj, rel=E_TOL)
     assert r_eam["Ecold"] == pytest.approx(e_eam, rel=E_TOL)
+
+
+def test_langevin_first_50_steps_with_a_temperature_update(ctx):
+    """The embedded-atom Langevin shapes: 50 GJF steps with a temperature
+    update at step 30 against the oracle, per step (noise as in
+    test_gpu_nvt.py: the same Philox words, Gaussians in FP32 on the device)."""
+    cell = ecell(4.4, 14.0, 4, cell_id=6)
+    n = 50
+    x0, v0, Ec = oracle.lift(cell)
+    ref = oracle.run(cell, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(30,), energy_every=5,
+                                           ensemble=1, gamma=1.0), x=x0, v=v0, Ecold_total=Ec, n_recF=n + 1)
+    sch = m.make_schedule(200, 100, (30,), 10, 5, ensemble=m.NVT_LANGEVIN, gamma=1.0)
+    print(f"eam langevin trajectory {cell}", flush=True)
+    h = m.mdeos_lift_from_state(ctx, gspec(cell), sch, x0, v0)
+    F, K, U, W = m.mdeos_debug_trajectory(ctx, h, n, cell.N)
+    m.mdeos_release(ctx, [h])
+    fn = np.array([np.linalg.norm(ref.F[k]) for k in range(n + 1)])
+    ferr = np.array([np.linalg.norm(F[k] - ref.F[k]) / max(fn[k], fn[-1]) for k in range(n + 1)])
+    den = np.maximum(np.abs(ref.U), ref.K)
+    uerr, kerr = np.abs(U - ref.U) / den, np.abs(K - ref.K) / den
+    print(f"  max rel err: F {ferr.max():.2e} U {uerr.max():.2e} K {kerr.max():.2e}; "
+          f"K jump at the update {ref.K[30] / ref.K[29]:.3f}", flush=True)
+    assert ferr.max() <= F_TOL, (ferr.argmax(), ferr.max())
+    assert uerr.max() <= E_TOL and kerr.max() <= E_TOL
+
+
+def test_langevin_batch_is_bitwise_equal_to_alone(ctx):
+    w = wl.eam_cu().subset(np.arange(5, 4096, 256))
+    specs, _ = m.specs_from_workload(w)
+    sch = m.make_schedule(300, 100, (100, 200), ensemble=m.NVT_LANGEVIN, gamma=1.0)
+    print(f"eam langevin batch of {w.n}", flush=True)
+    batch = m.mdeos_eval_batch(ctx, specs, sch)
+    assert not (batch["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)).any()
+    for i in (0, w.n - 1):
+        alone = m.mdeos_eval_batch(ctx, (m.CellSpec * 1)(specs[i]), sch)[0]
+        assert alone.tobytes() == batch[i].tobytes(), i

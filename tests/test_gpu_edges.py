@@ -1,0 +1,73 @@
+"""Edge cases on the GPU, through the C ABI: empty calls, stale handles, and
+the degenerate limit of the method.
+
+With no thermal energy (e -> 0 above the cold lattice, Eq. Tcontribution)
+the lifted box stays on its lattice, so the restricted pressure must approach
+the cold lattice's, W_lattice / (3V). That value comes from the oracle's
+lattice virial, which the oracle pins tie to -dE_cold/dV of an independent
+shell sum. Near the limit the crystal is harmonic: P - P_cold grows linearly
+in e, and the kinetic energy holds half of N e (equipartition).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06012_amd import mdeos as m
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = m.mdeos_create()
+    yield c
+    m.mdeos_destroy(c)
+
+
+def test_empty_calls(ctx):
+    none = (m.CellSpec * 0)()
+    sch = m.make_schedule(10, 10, (), 2)
+    print("empty calls", flush=True)
+    assert m.mdeos_eval_batch(ctx, none, sch).size == 0
+    assert m.mdeos_eval_plain(ctx, none, sch).size == 0
+    h = m.mdeos_lift(ctx, none, sch)
+    assert len(h) == 0
+    m.mdeos_advance(ctx, h, 10)
+    assert m.mdeos_restrict(ctx, h).size == 0
+    m.mdeos_release(ctx, h)
+
+
+def test_stale_handles_are_rejected(ctx):
+    sch = m.make_schedule(20, 10, (), 2)
+    h = m.mdeos_lift(ctx, m.make_specs(0.8, 1.0, 3, 2.5, 0.004, 1, 0), sch)
+    m.mdeos_advance(ctx, h, 10 ** 6)
+    m.mdeos_release(ctx, h)
+    for call in (lambda: m.mdeos_advance(ctx, h, 5), lambda: m.mdeos_restrict(ctx, h),
+                 lambda: m.mdeos_release(ctx, h)):
+        with pytest.raises(m.MdeosError) as e:
+            call()
+        assert e.value.status == m.INVALID_ARG
+
+
+@pytest.mark.parametrize("rho", [1.1, 1.0])
+def test_cold_crystal_limit(ctx, rho):
+    n_c, rc = 4, 2.5
+    N = 4 * n_c ** 3
+    L = oracle.box_length(n_c, rho)
+    _, _, W = oracle.forces(oracle.lattice(n_c, rho), L, rc)
+    P_cold = W / (3 * L ** 3)
+    sch = m.make_schedule(400, 200, (100, 200), 4)
+    print(f"cold crystal limit rho {rho}: P_cold {P_cold:.6f}", flush=True)
+    res = {}
+    for e in (1e-3, 1e-5):
+        r = m.mdeos_eval_batch(ctx, m.make_specs(rho, e, n_c, rc, 0.004, 3, 0), sch)[0]
+        assert r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW | m.CELL_ENERGY_BELOW_COLD) == 0
+        res[e] = r
+        print(f"  e {e}: P {r['P']:.7f} (P - P_cold {r['P'] - P_cold:+.3e}), T {r['T']:.3e}, "
+              f"E_cold/N {r['Ecold']:.6f}", flush=True)
+    assert res[1e-5]["Ecold"] * N == pytest.approx(oracle.ecold(n_c, rho, rc), rel=1e-6)
+    assert abs(res[1e-5]["P"] - P_cold) <= 1e-4
+    ratio = (res[1e-3]["P"] - P_cold) / (res[1e-5]["P"] - P_cold)
+    assert 70.0 <= ratio <= 140.0, ratio
+    for e, r in res.items():
+        assert 0.30 <= r["T"] / e <= 0.37, (e, r["T"])

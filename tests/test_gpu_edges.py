@@ -71,3 +71,36 @@ def test_cold_crystal_limit(ctx, rho):
     assert 70.0 <= ratio <= 140.0, ratio
     for e, r in res.items():
         assert 0.30 <= r["T"] / e <= 0.37, (e, r["T"])
+
+
+def test_capacity_overflow_is_reported_and_contained(ctx):
+    """A state packed into a small cluster (spacing 0.55, far denser than the
+    density the capacities are planned for, and more than rl from every face,
+    so no ghost images) overflows the neighbour capacity at its first list
+    build. The cell stops with CELL_OVERFLOW before any
+    force pass, and a normal cell advanced in the same launch is bitwise equal
+    to itself run alone."""
+    n_c, rho, N = 4, 0.3, 256
+    spec = m.make_specs(rho, 1.0, n_c, 2.5, 0.004, 1, 0)[0]
+    L = oracle.box_length(n_c, rho)
+    plan = m.mdeos_plan(spec, 0.4)
+    g = np.arange(7)
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)[:N] * 0.55
+    x = pts - pts.mean(axis=0) + L / 2
+    assert x.min() > plan.rl and x.max() < L - plan.rl  # no ghost images: only the list overflows
+    d = x[:, None, :] - x[None, :, :]
+    nmax = int(((d ** 2).sum(-1) < plan.rl ** 2).sum(1).max()) - 1
+    assert nmax > plan.list_cap, (nmax, plan.list_cap)
+    sch = m.make_schedule(50, 20, (), 2)
+    good_spec = m.make_specs(rho, 1.0, n_c, 2.5, 0.004, 2, 1)
+    print(f"capacity overflow: cluster with up to {nmax} neighbours, list capacity {plan.list_cap}", flush=True)
+    bad = m.mdeos_lift_from_state(ctx, spec, sch, x, np.zeros_like(x))
+    good = m.mdeos_lift(ctx, good_spec, sch)[0]
+    m.mdeos_advance(ctx, [bad, good], 10 ** 6)
+    r = m.mdeos_restrict(ctx, [bad, good])
+    m.mdeos_release(ctx, [bad, good])
+    print(f"  status {r['status'].tolist()}, max_list {r['max_list'].tolist()}", flush=True)
+    assert r[0]["status"] & m.CELL_OVERFLOW
+    assert r[1]["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) == 0
+    alone = m.mdeos_eval_batch(ctx, good_spec, sch)[0]
+    assert alone.tobytes() == r[1].tobytes()

@@ -1,6 +1,7 @@
 """The toy continuum driver on the device EOS: a piston driven into a
-Lennard-Jones fluid, every zone's pressure from its own MD box at every
-stage of every step (the EOS is called at every point and step, Sec. IV).
+Lennard-Jones fluid, and into the embedded-atom stand-in for copper, every
+zone's pressure from its own MD box at every stage of every step (the EOS is
+called at every point and step, Sec. IV).
 
 Checks, each fixed by the continuum equations rather than by the oracle:
   - no cell fails and no zone's energy falls to the cold lattice;
@@ -41,6 +42,65 @@ def _front(x, rho, level):
     return xc[k] + f * (xc[k + 1] - xc[k])
 
 
+def _run_piston(eos, rho1, e1, up, label):
+    """Drives the piston until the front (5 % density rise) passes 3/4 of the
+    tube; returns the final state, the (t, x, rho) history, p1, E0 and the
+    wall time."""
+    s = Lagrangian1D.tube(N_ZONES, LENGTH, (rho1, e1), (rho1, e1), eos, u_left=up)
+    p1 = float(np.mean(s.p))
+    E0 = s.total_energy()
+    hist = []
+    t0 = time.perf_counter()
+    while True:
+        s.step()
+        hist.append((s.t, s.x.copy(), s.rho.copy()))
+        xf = _front(s.x, s.rho, rho1 * 1.05)
+        if len(hist) % 25 == 0:
+            print(f"  {label} step {len(hist)} t {s.t:.4f} front {xf:.2f}", flush=True)
+        if xf > 0.75 * LENGTH or len(hist) >= 600:
+            break
+    return s, hist, p1, E0, time.perf_counter() - t0
+
+
+def _check_piston(eos, s, hist, rho1, e1, p1, E0, up, ctx, fresh_kw, tol=(0.03, 0.05, 0.05)):
+    """Energy = piston work; Rankine-Hugoniot jumps with the fitted shock
+    speed; plateau pressure = fresh lifts at the plateau state."""
+    assert eos.failed == 0 and eos.floored == 0
+    assert not (eos.last["status"] & m.CELL_COLD_RELIFT).any()
+    dE = s.total_energy() - E0
+    print(f"energy: gained {dE:.6f}, piston work {s.wall_work:.6f}", flush=True)
+    assert abs(dE - s.wall_work) < 1e-9 * abs(s.wall_work)
+    xc = 0.5 * (s.x[1:] + s.x[:-1])
+    xf = _front(s.x, s.rho, rho1 * 1.05)
+    plat = (xc > s.x[0] + 4.0) & (xc < xf - 4.0)
+    assert plat.sum() >= 10
+    rho2, p2, e2 = s.rho[plat].mean(), s.p[plat].mean(), s.e[plat].mean()
+    u2 = 0.5 * (s.u[1:] + s.u[:-1])[plat].mean()
+    level = 0.5 * (rho1 + rho2)
+    ts = np.array([h[0] for h in hist])
+    xs = np.array([_front(h[1], h[2], level) for h in hist])
+    late = ts > 0.5 * ts[-1]
+    Us = np.polyfit(ts[late], xs[late], 1)[0]
+    mass = rho2 * (Us - up) / (rho1 * Us) - 1
+    mom = (p2 - p1) / (rho1 * Us * up) - 1
+    ene = (e2 - e1) / (0.5 * (p1 + p2) * (1 / rho1 - 1 / rho2)) - 1
+    print(f"plateau: rho2 {rho2:.4f} p2 {p2:.4f} (p1 {p1:.4f}) e2-e1 {e2 - e1:.4f} u2 {u2:.4f}; "
+          f"Us {Us:.4f}; RH residuals mass {mass:+.4f} momentum {mom:+.4f} energy {ene:+.4f}", flush=True)
+    assert abs(u2 / up - 1) < 0.02
+    assert abs(mass) < tol[0] and abs(mom) < tol[1] and abs(ene) < tol[2]
+    ec2 = eos.cold_curve([rho2])[0]
+    R = 16
+    specs = m.make_specs(np.full(R, rho2), np.full(R, e2 - ec2), fresh_kw["n_c"], fresh_kw["rc"], fresh_kw["dt"],
+                         np.arange(100, 100 + R), 0)
+    fresh = m.mdeos_eval_batch(ctx, specs, eos.cold)
+    pf, pf_se = fresh["P"].mean(), fresh["P"].std(ddof=1) / np.sqrt(R)
+    p_sd = s.p[plat].std(ddof=1)
+    bar = 3 * np.hypot(pf_se, p_sd / np.sqrt(plat.sum())) + 0.02 * abs(p2)
+    print(f"fresh lifts at the plateau state: P {pf:.4f} +- {pf_se:.4f}; plateau {p2:.4f} (zone sd {p_sd:.4f}); "
+          f"bar {bar:.4f}", flush=True)
+    assert abs(pf - p2) < bar
+
+
 @pytest.fixture(scope="module")
 def ctx():
     c = m.mdeos_create()
@@ -51,59 +111,9 @@ def ctx():
 def test_piston_into_lj_fluid_with_the_md_eos(ctx):
     print(f"piston into LJ fluid: {N_ZONES} zones, rho1 {RHO1}, e1 {E_MD1} above cold, up {UP}", flush=True)
     eos = MDEOS(N_ZONES, n_c=4, rc=2.5, dt=0.004, seed=3, ctx=ctx)
-    ec1 = eos.cold_curve([RHO1])[0]
-    e1 = E_MD1 + ec1
-    s = Lagrangian1D.tube(N_ZONES, LENGTH, (RHO1, e1), (RHO1, e1), eos, u_left=UP)
-    p1 = float(np.mean(s.p))
-    E0 = s.total_energy()
-    hist = []
-    t0 = time.perf_counter()
-    while s.t < 1e3:
-        s.step()
-        hist.append((s.t, s.x.copy(), s.rho.copy()))
-        if len(hist) % 25 == 0:
-            print(f"  step {len(hist)} t {s.t:.3f} dt {hist[-1][0] - hist[-2][0]:.4f} "
-                  f"front {_front(s.x, s.rho, RHO1 * 1.05):.2f}", flush=True)
-        if _front(s.x, s.rho, RHO1 * 1.05) > 0.75 * LENGTH or len(hist) >= 600:
-            break
-    wall = time.perf_counter() - t0
-    assert eos.failed == 0 and eos.floored == 0
-    assert not (eos.last["status"] & m.CELL_COLD_RELIFT).any()
-    dE = s.total_energy() - E0
-    print(f"energy: gained {dE:.6f}, piston work {s.wall_work:.6f}", flush=True)
-    assert abs(dE - s.wall_work) < 1e-9 * abs(s.wall_work)
-
-    # the plateau: away from the piston and from the front
-    xc = 0.5 * (s.x[1:] + s.x[:-1])
-    xf = _front(s.x, s.rho, RHO1 * 1.05)
-    plat = (xc > s.x[0] + 4.0) & (xc < xf - 4.0)
-    assert plat.sum() >= 10
-    rho2, p2, e2 = s.rho[plat].mean(), s.p[plat].mean(), s.e[plat].mean()
-    u2 = 0.5 * (s.u[1:] + s.u[:-1])[plat].mean()
-    level = 0.5 * (RHO1 + rho2)
-    ts = np.array([h[0] for h in hist])
-    xs = np.array([_front(h[1], h[2], level) for h in hist])
-    late = ts > 0.5 * ts[-1]
-    Us = np.polyfit(ts[late], xs[late], 1)[0]
-    mass = rho2 * (Us - UP) / (RHO1 * Us) - 1
-    mom = (p2 - p1) / (RHO1 * Us * UP) - 1
-    ene = (e2 - e1) / (0.5 * (p1 + p2) * (1 / RHO1 - 1 / rho2)) - 1
-    print(f"plateau: rho2 {rho2:.4f} p2 {p2:.4f} (p1 {p1:.4f}) e2-e1 {e2 - e1:.4f} u2 {u2:.4f}; "
-          f"Us {Us:.4f}; RH residuals mass {mass:+.4f} momentum {mom:+.4f} energy {ene:+.4f}", flush=True)
-    assert abs(u2 / UP - 1) < 0.02
-    assert abs(mass) < 0.03 and abs(mom) < 0.05 and abs(ene) < 0.05
-
-    # the same (rho, e) from fresh lifts: 16 replicas of the cold schedule
-    ec2 = eos.cold_curve([rho2])[0]
-    R = 16
-    specs = m.make_specs(np.full(R, rho2), np.full(R, e2 - ec2), 4, 2.5, 0.004, np.arange(100, 100 + R), 0)
-    fresh = m.mdeos_eval_batch(ctx, specs, eos.cold)
-    pf, pf_se = fresh["P"].mean(), fresh["P"].std(ddof=1) / np.sqrt(R)
-    p_sd = s.p[plat].std(ddof=1)
-    tol = 3 * np.hypot(pf_se, p_sd / np.sqrt(plat.sum())) + 0.02 * abs(p2)
-    print(f"fresh lifts at the plateau state: P {pf:.4f} +- {pf_se:.4f}; plateau {p2:.4f} (zone sd {p_sd:.4f}); "
-          f"bar {tol:.4f}", flush=True)
-    assert abs(pf - p2) < tol
+    e1 = E_MD1 + eos.cold_curve([RHO1])[0]
+    s, hist, p1, E0, wall = _run_piston(eos, RHO1, e1, UP, "lj")
+    _check_piston(eos, s, hist, RHO1, e1, p1, E0, UP, ctx, dict(n_c=4, rc=2.5, dt=0.004))
 
     # cost per zone call (a call is one EOS evaluation of one zone)
     steps = len(hist)
@@ -124,3 +134,23 @@ def test_piston_into_lj_fluid_with_the_md_eos(ctx):
           f"{steps} hydro steps, {2 * steps + 1} EOS calls of {N_ZONES} zones in {wall:.2f} s", flush=True)
     assert md_warm < md_cold
     eos.close()
+
+
+def test_piston_into_eam_copper():
+    """The same problem in the embedded-atom stand-in for copper, the paper's
+    application material (reduced units: a = 3.6153 A, eps = 0.012382 eV):
+    the fitted lattice (rho 4.0 per a^3), e 3.0 above the cold lattice (T about
+    e / 3 for a harmonic crystal, about 150 K), a piston at 7.3 a/tau (about
+    1 km/s)."""
+    rho1, e_md1, up = 4.0, 3.0, 7.3
+    ctx = m.mdeos_create(potential=m.POT_EAM)
+    try:
+        print(f"piston into EAM copper: {N_ZONES} zones, rho1 {rho1}, e1 {e_md1} above cold, up {up}", flush=True)
+        eos = MDEOS(N_ZONES, n_c=4, rc=1.5, dt=0.001, seed=4, ctx=ctx)
+        e1 = e_md1 + eos.cold_curve([rho1])[0]
+        s, hist, p1, E0, wall = _run_piston(eos, rho1, e1, up, "eam")
+        print(f"  {len(hist)} steps in {wall:.2f} s", flush=True)
+        _check_piston(eos, s, hist, rho1, e1, p1, E0, up, ctx, dict(n_c=4, rc=1.5, dt=0.001))
+        eos.close()
+    finally:
+        m.mdeos_destroy(ctx)

@@ -8,8 +8,9 @@ staggered mesh: node positions x and velocities u (both at whole steps), zone
 masses m, specific volume v = (x_{j+1} - x_j) / m, specific internal energy e,
 pressure from the EOS (Eq. EOS). Shocks are captured with a quadratic plus
 linear artificial viscosity active in compression (the Wilkins form the paper
-cites, Sec. II.A). A step is a predictor-corrector with velocity averaging
-(the two-stage scheme of the paper's continuum code), with nodal forces
+cites, Sec. II.A). A step is a predictor-corrector with velocity averaging,
+an explicit energy-conserving time step like the paper's continuum solver
+uses (Sec. II.A), with nodal forces
 F_i = (p + q)_{i-1} - (p + q)_i and, for a stage of length h from state n,
     u' = u^n + h F(p + q) / M,   ubar = (u^n + u') / 2,   x' = x^n + h ubar
     e' = e^n - h (p + q) (ubar_{j+1} - ubar_j) / m_j,     p' = EOS(1 / v', e')
@@ -20,10 +21,12 @@ internal energy changes only by the work of the walls (to rounding). The
 right wall is rigid; the left may move at a prescribed speed (a piston), and
 the work it does is kept in wall_work. The EOS is called twice per step.
 
-Units: whatever the EOS uses; with the MD EOS they are reduced LJ units with
-unit atomic mass, so the mass density is the number density rho* and e is
-the energy per atom measured from the cold lattice (the energy zero of the
-lifting operator, Sec. III).
+Units: those of the EOS. With the MD EOS they are the reduced units of the
+context's potential (LJTS: sigma and eps; embedded-atom form: the lattice
+parameter a and eps) with unit atomic mass, so the mass density is the number
+density. The hydro's e has a fixed zero; by default the MD adapter hands the
+lift the energy above the cold lattice at each zone's own density (the
+lifting operator's energy zero, Sec. III).
 """
 from __future__ import annotations
 

@@ -8,10 +8,12 @@
  * lifting operator maps (rho, e) to a periodic FCC box of N = 4 n_c^3 atoms
  * with velocities that carry the energy e above the cold lattice (Sec. III,
  * Eqs. numdens, numAtoms, Tcontribution); the box is advanced with velocity
- * Verlet (Sec. II.B) in a truncated-shifted Lennard-Jones fluid in reduced
- * units; the restricting operator returns the time average of one third of
- * the trace of the kinetic + virial stress (Sec. III, Eq. stress) and the
- * temperature, with block standard errors.
+ * Verlet or the GJF Langevin integrator (Sec. II.B), for a truncated-shifted
+ * Lennard-Jones fluid or a many-body material of the embedded-atom form
+ * (Eq. Etot) in reduced units; the restricting operator returns the time
+ * average of one third of the trace of the kinetic + virial stress (Sec. III,
+ * Eq. stress), the full stress tensor and the temperature, with block
+ * standard errors.
  *
  * Conventions for every call:
  *   - Host arrays passed in are read during the call only; host arrays passed
@@ -61,8 +63,8 @@ typedef struct {
     double rho;               /* reduced number density rho* > 0 (n = rho in reduced units) */
     double e;                 /* specific internal energy per atom above the cold lattice, > 0 */
     int n_c;                  /* FCC cells per edge, 1..MDEOS_MAX_NC; N = 4 n_c^3 */
-    float rc;                 /* LJTS cutoff, 0 < rc < L */
-    double dt;                /* velocity-Verlet time step, > 0 */
+    float rc;                 /* cutoff of the context's potential, 0 < rc < L */
+    double dt;                /* MD time step, > 0 */
     unsigned long long seed;  /* Philox4x64-10 key word 0 */
     long long cell_id;        /* Philox4x64-10 key word 1 (and the caller's cell label) */
 } mdeos_cell_spec;
@@ -209,8 +211,9 @@ mdeos_status mdeos_lift_from_state(mdeos_ctx* ctx, const mdeos_cell_spec* spec, 
 mdeos_status mdeos_warm_start(mdeos_ctx* ctx, int n, const mdeos_handle* h, const double* rho, const double* e,
                               const mdeos_schedule* sched, void* stream);
 
-/* Advances each cell by up to n_steps velocity-Verlet steps (never past its
- * schedule's end), in one persistent launch per size bucket. */
+/* Advances each cell by up to n_steps MD steps (velocity Verlet or GJF, as
+ * its schedule's ensemble says; never past the schedule's end), in one
+ * persistent launch per size bucket. */
 mdeos_status mdeos_advance(mdeos_ctx* ctx, int n, const mdeos_handle* h, int n_steps, void* stream);
 
 /* Restricting operator: writes one result per handle (blocks on the stream).

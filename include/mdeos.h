@@ -255,7 +255,9 @@ mdeos_status mdeos_debug_forces(mdeos_ctx* ctx, const mdeos_cell_spec* spec, con
 /* Advances a resident cell by n_steps, one launch per step, with E_pot
  * computed every step, and records forces (F: (n_steps+1) x N x 3, may be
  * NULL) and K, U, W (n_steps+1 each, may be NULL) for the starting state and
- * after each step. */
+ * after each step. A pending lift or warm start runs first, so the starting
+ * state of a warm-started cell is the re-targeted one (after its step-0
+ * re-pin). */
 mdeos_status mdeos_debug_trajectory(mdeos_ctx* ctx, mdeos_handle h, int n_steps, double* F, double* K, double* U,
                                     double* W);
 

@@ -1373,7 +1373,16 @@ extern "C" mdeos_status mdeos_debug_trajectory(mdeos_ctx* ctx, mdeos_handle h, i
     }
     return MDEOS_OK;
   };
-  mdeos_status st = record(0);
+  // a cell whose lift or warm start is still pending (a warm start only marks
+  // the cell) runs that phase first, so that step 0 is the re-targeted state
+  CellRec r0;
+  mdeos_status st = c->download_record(slot, r0, s);
+  if (st == MDEOS_OK && (r0.phase == PH_COLD || r0.phase == PH_STATE || r0.phase == PH_WARM)) {
+    std::vector<Bucket> b;
+    c->make_buckets(idx, b, -1);
+    st = c->run_buckets(b, -1, s, false);
+  }
+  if (st == MDEOS_OK) st = record(0);
   for (int k = 1; k <= n_steps && st == MDEOS_OK; ++k) {
     std::vector<Bucket> b;
     c->make_buckets(idx, b, 1);

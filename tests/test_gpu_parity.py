@@ -169,3 +169,33 @@ def test_chunked_equals_whole_bitwise(ctx):
     chunked = m.mdeos_restrict(ctx, h)
     m.mdeos_release(ctx, h)
     assert whole.tobytes() == chunked.tobytes()
+
+
+@pytest.mark.parametrize("rho1,e1", [(0.9, 2.0), (0.7, 1.2)], ids=["compress", "expand"])
+def test_warm_start_first_50_steps(ctx, rho1, e1):
+    """Warm start (Sec. III, re-targeting a resident box): the oracle
+    equilibrates a box at (0.8, 1.5); the device lifts from those exact bits;
+    both then dilate x by L'/L, recompute E_cold at rho', re-pin to e' at step
+    0 of the new schedule and run 50 steps, compared per step."""
+    cell0 = oracle.Cell(rho=0.8, e=1.5, n_c=4, rc=2.5, dt=0.004, seed=5, cell_id=7)
+    r0 = oracle.run(cell0, oracle.Schedule(n_steps=200, n_avg=100, n_blocks=2, rescale_steps=(50,)))
+    cell1 = oracle.Cell(rho=rho1, e=e1, n_c=4, rc=2.5, dt=0.004, seed=5, cell_id=7)
+    n = 50
+    xw = oracle.warm_start_state(r0.x, 4, 0.8, rho1)
+    ref = oracle.run(cell1, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(0,), energy_every=5),
+                     x=xw, v=r0.v, Ecold_total=oracle.ecold(4, rho1, 2.5), n_recF=n + 1)
+    print(f"warm start 0.8 -> {rho1}, e {e1}", flush=True)
+    h = m.mdeos_lift_from_state(ctx, gspec(cell0), m.make_schedule(100, 50, (), 2), r0.x, r0.v)
+    m.mdeos_warm_start(ctx, [h], rho1, e1, m.make_schedule(200, 100, (0,), 10, 5))
+    F, K, U, W = m.mdeos_debug_trajectory(ctx, h, n, cell1.N)
+    m.mdeos_release(ctx, [h])
+    fn = np.array([np.linalg.norm(ref.F[k]) for k in range(n + 1)])
+    ferr = np.array([np.linalg.norm(F[k] - ref.F[k]) / max(fn[k], fn[-1]) for k in range(n + 1)])
+    den = np.maximum(np.abs(ref.U), ref.K)
+    uerr, kerr = np.abs(U - ref.U) / den, np.abs(K - ref.K) / den
+    werr = np.abs(W - ref.W) / np.maximum(np.abs(ref.W), den)
+    print(f"  max rel err: F {ferr.max():.2e} U {uerr.max():.2e} K {kerr.max():.2e} W {werr.max():.2e}; "
+          f"K at step 0: gpu {K[0]:.6f} oracle {ref.K[0]:.6f}", flush=True)
+    assert ferr.max() <= F_TOL, (ferr.argmax(), ferr.max())
+    assert uerr.max() <= E_TOL and kerr.max() <= E_TOL
+    assert werr.max() <= 1e-5

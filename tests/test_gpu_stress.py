@@ -65,3 +65,35 @@ def test_trace_over_three_is_the_pressure(ctx):
     scale = np.maximum(np.abs(res["P"]), rho * res["T"])
     assert np.all(np.abs(tr3 - res["P"]) <= 1e-5 * scale), np.abs(tr3 - res["P"]) / scale
     assert np.all(np.isfinite(res["stress"]))
+
+
+EAM_CASES = [
+    (oracle.Cell(rho=4.4, e=wl.e_from_T(14.0, 256).item(), n_c=4, rc=1.5, dt=0.001, seed=7, cell_id=1, potential=1), 0),
+    (oracle.Cell(rho=4.4, e=wl.e_from_T(10.0, 108).item(), n_c=3, rc=1.5, dt=0.001, seed=7, cell_id=3, potential=1), 0),
+    (oracle.Cell(rho=5.5, e=wl.e_from_T(30.0, 256).item(), n_c=4, rc=1.5, dt=0.001, seed=7, cell_id=2, potential=1), 1),
+]
+EAM_IDS = ["eam-256", "eam-multi-image-108", "eam-langevin-256"]
+
+
+@pytest.fixture(scope="module")
+def eam_ctx():
+    c = m.mdeos_create(potential=m.POT_EAM)
+    yield c
+    m.mdeos_destroy(c)
+
+
+@pytest.mark.parametrize("cell,ens", EAM_CASES, ids=EAM_IDS)
+def test_eam_stress_matches_oracle_from_identical_bits(eam_ctx, cell, ens):
+    """The embedded-atom force walk accumulates its own pair virial tensor
+    (the pair-decomposed forces of Eq. Etot); same bar as the LJTS cases."""
+    test_stress_matches_oracle_from_identical_bits(eam_ctx, cell, ens)
+
+
+def test_eam_trace_over_three_is_the_pressure(eam_ctx):
+    w = wl.eam_cu().subset(np.arange(3, 4096, 128))
+    specs, _ = m.specs_from_workload(w)
+    res = m.mdeos_eval_batch(eam_ctx, specs, m.make_schedule(600, 300, (100, 200), 10, 1))
+    tr3 = res["stress"][:, :3].mean(axis=1)
+    scale = np.maximum(np.abs(res["P"]), w.rho * res["T"])
+    assert np.all(np.abs(tr3 - res["P"]) <= 1e-5 * scale), np.abs(tr3 - res["P"]) / scale
+    assert np.all(np.isfinite(res["stress"]))

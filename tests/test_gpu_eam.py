@@ -127,6 +127,31 @@ def test_first_50_steps(ctx, cell):
     assert werr.max() <= W_TOL
 
 
+def test_kahan_mode_first_50_steps():
+    """The compensated-FP32 accumulation of the embedded-atom walk, per step
+    against the oracle (same bars as the FP64 mode)."""
+    cell = CELLS[0]
+    n = 50
+    x0, v0, Ec = oracle.lift(cell)
+    ref = oracle.run(cell, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(20,), energy_every=5),
+                     x=x0, v=v0, Ecold_total=Ec, n_recF=n + 1)
+    kctx = m.mdeos_create(potential=m.POT_EAM, precision=m.PREC_KAHAN)
+    try:
+        print(f"eam kahan trajectory {cell}", flush=True)
+        h = m.mdeos_lift_from_state(kctx, gspec(cell), m.make_schedule(200, 100, (20,), 10, 5), x0, v0)
+        F, K, U, W = m.mdeos_debug_trajectory(kctx, h, n, cell.N)
+        m.mdeos_release(kctx, [h])
+    finally:
+        m.mdeos_destroy(kctx)
+    fn = np.array([np.linalg.norm(ref.F[k]) for k in range(n + 1)])
+    ferr = np.array([np.linalg.norm(F[k] - ref.F[k]) / max(fn[k], fn[-1]) for k in range(n + 1)])
+    den = np.maximum(np.abs(ref.U), ref.K)
+    uerr, kerr = np.abs(U - ref.U) / den, np.abs(K - ref.K) / den
+    werr = np.abs(W - ref.W) / np.maximum(np.abs(ref.W), np.abs(ref.U))
+    print(f"  max rel err: F {ferr.max():.2e} U {uerr.max():.2e} K {kerr.max():.2e} W {werr.max():.2e}", flush=True)
+    assert ferr.max() <= F_TOL and uerr.max() <= E_TOL and kerr.max() <= E_TOL and werr.max() <= W_TOL
+
+
 def test_alone_batch_and_chunked_are_bitwise_equal(ctx):
     w = wl.eam_cu().subset(np.arange(0, 4096, 128))
     specs, sch = m.specs_from_workload(w)

@@ -37,8 +37,8 @@ def queries(n_cells=6, per_cell=3, seed=1):
     return out
 
 
-def serve_all(ctx, qs, chunk, timeout=90.0):
-    m.mdeos_serve_start(ctx, sched(COLD), sched(WARM), RC, DT, SEED, chunk_steps=chunk)
+def serve_all(ctx, qs, chunk, timeout=90.0, rc=RC, dt=DT):
+    m.mdeos_serve_start(ctx, sched(COLD), sched(WARM), rc, dt, SEED, chunk_steps=chunk)
     tickets = []
     for c, rho, e, n_c in qs:
         tickets.append(m.mdeos_serve_submit(ctx, c, rho, e, n_c, m.mdeos_serve_now(ctx)))
@@ -54,11 +54,11 @@ def serve_all(ctx, qs, chunk, timeout=90.0):
     return tickets, got, stats
 
 
-def alone(ctx, c, seq):
+def alone(ctx, c, seq, rc=RC, dt=DT):
     """The same query sequence of one cell through the batch API."""
     out = []
     _, rho, e, n_c = seq[0]
-    h = m.mdeos_lift(ctx, m.make_specs(rho, e, n_c, RC, DT, SEED, c), sched(COLD))
+    h = m.mdeos_lift(ctx, m.make_specs(rho, e, n_c, rc, dt, SEED, c), sched(COLD))
     m.mdeos_advance(ctx, h, 0 or 10 ** 6)
     out.append(m.mdeos_restrict(ctx, h)[0])
     for _, rho, e, n_c in seq[1:]:
@@ -86,6 +86,32 @@ def test_served_equals_alone_bitwise(chunk):
                 r = got[tk[k]]
                 assert r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) == 0
                 assert r.tobytes() == ref[k].tobytes(), (c, k, r, ref[k])
+    finally:
+        m.mdeos_destroy(ctx)
+
+
+def test_served_equals_alone_bitwise_embedded_atom():
+    """The serving loop on an embedded-atom context (densities per a^3)."""
+    ctx = m.mdeos_create(potential=m.POT_EAM)
+    try:
+        rng = np.random.default_rng(3)
+        qs = []
+        for q in range(3):
+            for c in range(4):
+                n_c = (3, 4)[c % 2]
+                T = rng.uniform(7.0, 20.0)
+                qs.append((c, float(rng.uniform(4.0, 5.0)), float(wl.e_from_T(T, 4 * n_c ** 3)), n_c))
+        print(f"serving {len(qs)} embedded-atom queries", flush=True)
+        tickets, got, stats = serve_all(ctx, qs, 50, rc=1.5, dt=0.001)
+        assert len(got) == len(qs), (len(got), stats)
+        for c in range(4):
+            seq = [q for q in qs if q[0] == c]
+            tk = [t for t, q in zip(tickets, qs) if q[0] == c]
+            ref = alone(ctx, c, seq, rc=1.5, dt=0.001)
+            for k in range(len(seq)):
+                r = got[tk[k]]
+                assert r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) == 0
+                assert r.tobytes() == ref[k].tobytes(), (c, k)
     finally:
         m.mdeos_destroy(ctx)
 

@@ -227,3 +227,26 @@ def test_langevin_batch_is_bitwise_equal_to_alone(ctx):
     for i in (0, w.n - 1):
         alone = m.mdeos_eval_batch(ctx, (m.CellSpec * 1)(specs[i]), sch)[0]
         assert alone.tobytes() == batch[i].tobytes(), i
+
+
+def test_langevin_minimum_image_4000_first_20_steps(ctx):
+    """The Langevin shape for embedded-atom boxes too large for ghost images
+    (4000 atoms, minimum image): 20 GJF steps with a temperature update at
+    step 10, per step against the oracle."""
+    cell = ecell(4.0, 14.0, 10, cell_id=9)
+    assert m.mdeos_plan(gspec(cell), 0.15).ext_cap == 4087
+    n = 20
+    x0, v0, Ec = oracle.lift(cell)
+    ref = oracle.run(cell, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(10,), energy_every=5,
+                                           ensemble=1, gamma=1.0), x=x0, v=v0, Ecold_total=Ec, n_recF=n + 1)
+    sch = m.make_schedule(200, 100, (10,), 10, 5, ensemble=m.NVT_LANGEVIN, gamma=1.0)
+    print(f"eam langevin minimum image {cell}", flush=True)
+    h = m.mdeos_lift_from_state(ctx, gspec(cell), sch, x0, v0)
+    F, K, U, W = m.mdeos_debug_trajectory(ctx, h, n, cell.N)
+    m.mdeos_release(ctx, [h])
+    fn = np.array([np.linalg.norm(ref.F[k]) for k in range(n + 1)])
+    ferr = np.array([np.linalg.norm(F[k] - ref.F[k]) / max(fn[k], fn[-1]) for k in range(n + 1)])
+    den = np.maximum(np.abs(ref.U), ref.K)
+    uerr, kerr = np.abs(U - ref.U) / den, np.abs(K - ref.K) / den
+    print(f"  max rel err: F {ferr.max():.2e} U {uerr.max():.2e} K {kerr.max():.2e}", flush=True)
+    assert ferr.max() <= F_TOL and uerr.max() <= E_TOL and kerr.max() <= E_TOL

@@ -20,6 +20,9 @@
 // Every reduction runs in a fixed order over groups of 64 consecutive atoms,
 // and neighbour lists are built in a deterministic order, so a cell's bits do
 // not depend on the launch shape, the batch it runs in, or chunk boundaries.
+// Sums of products are written as explicit fma chains: left to the compiler,
+// a + b * c + d * e can be fused in more than one way, and the choice may
+// differ between the launch shapes' instantiations.
 #pragma once
 #include <type_traits>
 
@@ -276,7 +279,7 @@ struct Box {
     Ndof = 3.0 * N - 3.0;
     double irc2 = 1.0 / ((double)c->rc * (double)c->rc);
     double irc6 = irc2 * irc2 * irc2;
-    u_shift = 4.0 * (irc6 * irc6 - irc6);
+    u_shift = 4.0 * fma(irc6, irc6, -irc6);
     if (EAM) {
       const double rcd = c->rc, irc = 1.0 / rcd;
       e_c6 = (float)(6.0 * irc6 * irc);
@@ -297,7 +300,8 @@ struct Box {
     seed = c->seed;
     cell_id = c->cell_id;
     {
-      const double cg = 0.5 * c->gamma * dt, b = 1.0 / (1.0 + cg), a = (1.0 - cg) / (1.0 + cg);
+      const double hg = 0.5 * c->gamma;
+      const double b = 1.0 / fma(hg, dt, 1.0), a = fma(-hg, dt, 1.0) / fma(hg, dt, 1.0);
       gjf_sb = sqrt(b);
       gjf_a_sb = a / gjf_sb;
       gamma_dt2 = 2.0 * c->gamma * dt;
@@ -575,7 +579,7 @@ struct Box {
               ddy = byi - PY(e4[u]);
               ddz = bzi - PZ(e4[u]);
             }
-            d2[u] = ddx * ddx + ddy * ddy + ddz * ddz;
+            d2[u] = fmaf(ddx, ddx, fmaf(ddy, ddy, ddz * ddz));
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
@@ -773,9 +777,9 @@ struct Box {
           if (ACC == ACC_FWUS) {
             // pair virial tensor d_a f_b with f = ff d (six components)
             const float fdx = ff * dx, fdy = ff * dy, fdz = ff * dz;
-            ax += fdx;
-            ay += fdy;
-            az += fdz;
+            ax = fmaf(ff, dx, ax);
+            ay = fmaf(ff, dy, ay);
+            az = fmaf(ff, dz, az);
             sxx = fmaf(fdx, dx, sxx);
             syy = fmaf(fdy, dy, syy);
             szz = fmaf(fdz, dz, szz);
@@ -818,7 +822,7 @@ struct Box {
         ud = (double)us - (double)uc;
       }
       wi[k] = ACC >= ACC_FW ? wd : 0.0;
-      ui[k] = ACC >= ACC_FWU ? 4.0 * ud - (double)cin * u_shift : 0.0;
+      ui[k] = ACC >= ACC_FWU ? fma(-(double)cin, u_shift, 4.0 * ud) : 0.0;
       cnt_in[k] = (ACC >= ACC_FWU && a < N) ? cin : 0;
       if (ACC == ACC_FWUS) {
         sv[0][k] = sxx; sv[1][k] = syy; sv[2][k] = szz;
@@ -866,8 +870,8 @@ struct Box {
           const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
           const float ir = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
           const float ir2 = ir * ir;
-          const float ir6 = ir2 * ir2 * ir2;
-          const float fr = fmaf(e_c6, r2 * ir, ir6 - e_k6);
+          const float ir4 = ir2 * ir2;
+          const float fr = fmaf(e_c6, r2 * ir, fmaf(ir4, ir2, -e_k6));
           rs += in ? fr : 0.0f;
         }
       };
@@ -933,9 +937,9 @@ struct Box {
           const float vir = ff * r2;
           if (ACC == ACC_FWUS) {
             const float fdx = ff * dx, fdy = ff * dy, fdz = ff * dz;
-            ax += fdx;
-            ay += fdy;
-            az += fdz;
+            ax = fmaf(ff, dx, ax);
+            ay = fmaf(ff, dy, ay);
+            az = fmaf(ff, dz, az);
             sxx = fmaf(fdx, dx, sxx);
             syy = fmaf(fdy, dy, syy);
             szz = fmaf(fdz, dz, szz);
@@ -957,7 +961,7 @@ struct Box {
             }
           }
           if (ACC >= ACC_FWU) {
-            const float e = in ? fmaf(e_c9, r2 * ir, ir6 * ir2 * ir - e_k9) : 0.0f;
+            const float e = in ? fmaf(e_c9, r2 * ir, fmaf(ir6 * ir2, ir, -e_k9)) : 0.0f;
             if (KAHAN) {
               const float y2 = e - uc, t2 = us + y2;
               uc = (t2 - us) - y2;
@@ -1044,7 +1048,7 @@ struct Box {
         ctl->sumT[b] += T;
         if (idx == 0) ctl->P_ref = P;
         const double dp = P - ctl->P_ref;
-        ctl->sumdP2 += dp * dp;
+        ctl->sumdP2 = fma(dp, dp, ctl->sumdP2);
         if (energy && (k % energy_every == 0 || k == n)) {
           ctl->sumU += U;
           ctl->nU += 1;
@@ -1229,7 +1233,7 @@ struct Box {
     double ka[APT], za[APT];
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-      ka[k] = valid(k) ? 0.5 * (vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]) : 0.0;
+      ka[k] = valid(k) ? 0.5 * fma(vx[k], vx[k], fma(vy[k], vy[k], vz[k] * vz[k])) : 0.0;
       za[k] = 0.0;
     }
     double K, z1, z2;
@@ -1269,7 +1273,7 @@ struct Box {
     for (int k = 0; k < APT; ++k) {
       if (valid(k)) {
         v0[k] -= m0; v1[k] -= m1; v2[k] -= m2;
-        ke[k] = 0.5 * (v0[k] * v0[k] + v1[k] * v1[k] + v2[k] * v2[k]);
+        ke[k] = 0.5 * fma(v0[k], v0[k], fma(v1[k], v1[k], v2[k] * v2[k]));
       } else {
         ke[k] = 0.0;
       }
@@ -1292,7 +1296,7 @@ struct Box {
   DEVI void record_step0(double U0, double W0) {
     double K = kinetic_now();
     if (is_rescale(0)) {
-      const double Kt = N * c->e - (U0 - Ecold);
+      const double Kt = fma((double)N, c->e, -(U0 - Ecold));
       if (Kt <= 0.0) {
         if (t == 0) ctl->status |= ST_BELOW_COLD;
       } else {
@@ -1381,7 +1385,7 @@ struct Box {
         fail_overflow(0);
         return;
       }
-      if (phase == PH_WARM && !(N * c->e - (U0 - Ec) > 0.0)) {
+      if (phase == PH_WARM && !(fma((double)N, c->e, -(U0 - Ec)) > 0.0)) {
         // no kinetic energy left above the new cold lattice: lift cold instead
         cold = true;
         if (t == 0) ctl->status |= ST_COLD_RELIFT;
@@ -1445,7 +1449,7 @@ struct Box {
             z[q] = fma(dt, vz[q], z[q]);
           }
           const float ex = (float)x[q] - bx[q], ey = (float)y[q] - by[q], ez = (float)z[q] - bz[q];
-          dm = fmaxf(dm, ex * ex + ey * ey + ez * ez);
+          dm = fmaxf(dm, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
         }
       }
       // owners write their atoms and ghost images (the last barrier of the
@@ -1510,7 +1514,7 @@ struct Box {
           vz[q] = fma(hdt, (double)fz[q], vz[q]);
         }
         const bool v = valid(q);
-        ka[q] = v ? 0.5 * (vx[q] * vx[q] + vy[q] * vy[q] + vz[q] * vz[q]) : 0.0;
+        ka[q] = v ? 0.5 * fma(vx[q], vx[q], fma(vy[q], vy[q], vz[q] * vz[q])) : 0.0;
         wa[q] = v ? 0.5 * wi[q] : 0.0;
         ua[q] = (v && energy) ? 0.5 * ui[q] : 0.0;
       }
@@ -1553,13 +1557,13 @@ struct Box {
               ctl->segN += 1;
             }
             const double Ubar = ctl->segN > 0 ? ctl->segU / ctl->segN : U;
-            Kt = N * c->e - (Ubar - Ecold);
+            Kt = fma((double)N, c->e, -(Ubar - Ecold));
             if (Kt > 0.0 && isfinite(Kt)) ctl->T_th = 2.0 * Kt / Ndof;
             ctl->segU = 0.0;
             ctl->segN = 0;
             ctl->seg_prev = k;
           } else {
-            Kt = N * c->e - (U - Ecold);  // energy re-pin with the instantaneous E_pot
+            Kt = fma((double)N, c->e, -(U - Ecold));  // energy re-pin with the instantaneous E_pot
           }
           ctl->do_rescale = (Kt > 0.0 && isfinite(Kt)) ? 1 : 0;
           ctl->lam = (Kt > 0.0) ? sqrt(Kt / K) : 1.0;

@@ -122,7 +122,7 @@ typedef struct {
 typedef struct {
     int device;                /* HIP device ordinal */
     size_t hbm_budget;         /* bytes of resident cell state the context may hold; 0 = 64 GiB */
-    float skin;                /* Verlet skin; <= 0 selects 0.4 (LJTS) or 0.15 (MDEOS_POT_EAM) */
+    float skin;                /* Verlet skin; <= 0 selects 0.4 (LJTS) or 0.5 (MDEOS_POT_EAM) */
     int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
     const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
     int precision;             /* how each atom sums its pair energies and virials (forces are FP32):
@@ -130,6 +130,12 @@ typedef struct {
     int potential;             /* the material of every cell of the context: MDEOS_POT_LJTS (default)
                                   or MDEOS_POT_EAM */
     double eam_c;              /* embedding strength c of MDEOS_POT_EAM; <= 0 selects 39.432 */
+    float prune_skin;          /* inner-list skin s_in: between list builds, every time an atom has moved
+                                  s_in / 2 the force walks switch to the list entries within rc + s_in.
+                                  Results are bit-identical with and without (dropped entries add exact
+                                  zeros). 0 selects none (LJTS) or 0.12 (MDEOS_POT_EAM); < 0 turns
+                                  it off; no effect when s_in >= skin, for lists held in LDS, or with
+                                  MDEOS_PREC_KAHAN. NaN or infinity: MDEOS_INVALID_ARG. */
 } mdeos_config;
 
 /* Per-atom accumulation of pair energy and virial terms. The box sums that

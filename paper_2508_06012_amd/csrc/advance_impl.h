@@ -43,6 +43,7 @@ struct Ctl {
   int n_ext;
   int wsum[17];
   float wmax[16];
+  float pmax[16];
   int do_rescale;
   int pad1;
   double lam;
@@ -182,6 +183,13 @@ struct Box {
   unsigned char* lds;
   PT* px;  // py = px + EXT, pz = px + 2 EXT
   uint16_t* list;  // [list_cap/8][n_pad][8]
+  // Inner lists (device memory, same shape): the entries of `list` within
+  // rc + prune_skin of the positions at the last prune, in list order. The
+  // force walks use them while `inner` is set; entries between rc and the
+  // list radius only ever add exact zeros, so the walk over either list
+  // gives the same bits.
+  uint16_t* ilist;
+  bool inner;
   uint16_t *tmp, *sorted;
   float* fpv;  // F'(rhobar) per position slot (embedded-atom forces; shares tmp/sorted, live outside list builds)
   int *cstart, *cfill, *scanbuf;
@@ -194,6 +202,8 @@ struct Box {
   int N, G, n_pad, list_cap, ncell, nce, R;
   float L, rl, rl2, rc2, inv_ce;
   float rlc2;  // (rl in cell edges)^2, widened by a relative 1e-4 so clipping stays conservative
+  float rin2, pthr;  // inner-list radius^2 (rc + prune_skin)^2; prune trigger (displacement^2)
+  bool prune_cell;   // this cell keeps inner lists
   double invLw;
   double Lw, dt, hdt;
   double V, Ndof, u_shift;
@@ -226,6 +236,8 @@ struct Box {
   double wi[APT], ui[APT];
   float sv[6][APT];  // per-atom pair virial tensor of a sampled step (xx, yy, zz, xy, xz, yz)
   int gofs[APT], gmask[APT], nblk[APT], cnt_in[APT];
+  int fnb[APT];                      // blocks of the list the force walks use (wave-uniform)
+  float prx[APT], pry[APT], prz[APT];  // positions at the last prune
   double pairs_t;  // ordered in-range pairs of this thread's atoms over sampled steps
   int esteps;      // sampled (energy) steps in this launch
 
@@ -234,6 +246,10 @@ struct Box {
     px = (PT*)(lds + lay.pos);
     list = LLDS ? (uint16_t*)(lds + lay.list)
                 : p.gl_list + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
+    ilist = (LLDS || p.gl_ilist == nullptr || p.kahan != 0)
+                ? nullptr
+                : p.gl_ilist + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
+    inner = false;
     tmp = (uint16_t*)(lds + lay.tmp);
     sorted = (uint16_t*)(lds + lay.sorted);
     cstart = (int*)(lds + lay.cstart);
@@ -273,6 +289,16 @@ struct Box {
     {
       const float rlc = rl * inv_ce * 1.0001f;
       rlc2 = rlc * rlc;
+    }
+    {
+      // Inner lists pay off only inside the skin. A pair dropped at a prune
+      // (r >= rc + ps) reaches rc only after the two atoms moved ps apart, so
+      // a prune follows as soon as any atom has moved ps / 2; the trigger sits
+      // 1 % below that, far above the FP32 rounding of the distances.
+      const float rcf = c->rc, ps = p.prune_skin;
+      prune_cell = ilist != nullptr && ps > 0.f && rl - rcf > ps;
+      rin2 = (rcf + ps) * (rcf + ps);
+      pthr = 0.98f * 0.25f * ps * ps;
     }
     invLw = 1.0 / c->Lw;
     V = c->V;
@@ -648,6 +674,7 @@ struct Box {
       cm = min(cm, list_cap);
       int nb = __builtin_amdgcn_readfirstlane((cm + 7) >> 3);
       nblk[k] = nb;
+      fnb[k] = nb;
       // pad every lane of the wave (also atoms past N) to nb blocks: with the
       // far-away sentinel, or (minimum image, where no point is far from all
       // atoms) with the atom itself, which the r^2 > 0 test drops
@@ -662,6 +689,7 @@ struct Box {
       }
     }
     if (over) ctl->overflow = 1;
+    inner = false;
     __syncthreads();
     bool ok = ctl->overflow == 0;
     if (t == 0) atomicMax(&c->max_ext, n_ext);
@@ -711,8 +739,12 @@ struct Box {
   // otherwise each term is promoted and summed in FP64.
   // Hands the list blocks of owned atom a (nb blocks of 8 entries, two 16-bit
   // byte offsets per word) to fn in order.
+  // The list the force walks use: the inner lists after a prune, otherwise
+  // the lists of the last build.
+  DEVI const uint16_t* force_list() const { return (!LLDS && inner) ? ilist : list; }
+
   template <class FN>
-  DEVI void walk_list(int a, int nb, FN&& fn) {
+  DEVI void walk_list(const uint16_t* base, int a, int nb, FN&& fn) {
     if (a < n_pad && nb > 0) {
       // Blocks are loaded one ahead into two alternating registers, so a
       // block's load latency (device memory when the list does not fit in
@@ -722,7 +754,7 @@ struct Box {
       // covers the load issued before it.
       // The scheduling barriers keep each load where it is issued (the
       // scheduler would otherwise sink it next to its use).
-      const uint4* row = reinterpret_cast<const uint4*>(list) + a;
+      const uint4* row = reinterpret_cast<const uint4*>(base) + a;
       uint4 e0 = row[0];
       for (int b = 0; b < nb; b += 2) {
         const uint4 e1 = row[min(b + 1, nb - 1) * n_pad];
@@ -734,6 +766,60 @@ struct Box {
         fn(e1);
       }
     }
+  }
+
+  // Inner lists from the current positions: the entries of each atom's list
+  // with r^2 < (rc + prune_skin)^2, in list order, each wave padded to its
+  // longest like the lists of a build. Every thread writes and later reads
+  // only the rows of its own atoms.
+  DEVI void prune() {
+    const char* pb = reinterpret_cast<const char*>(px);
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      const int a = t + k * BLOCK;
+      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
+      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      int cnt = 0;
+      auto block = [&](const uint4 ent) __attribute__((always_inline)) {
+        const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
+          const PT* q = reinterpret_cast<const PT*>(pb + off);
+          float dx, dy, dz;
+          if (MI) {
+            dx = (float)mimg(xi64 - q[0]);
+            dy = (float)mimg(yi64 - q[EXT]);
+            dz = (float)mimg(zi64 - q[2 * EXT]);
+          } else {
+            dx = xi - q[0];
+            dy = yi - q[EXT];
+            dz = zi - q[2 * EXT];
+          }
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          if (MI ? (r2 < rin2 && r2 > 0.0f) : r2 < rin2) {
+            // cnt never exceeds the entries of the outer row (< list_cap)
+            ilist[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)off;
+            ++cnt;
+          }
+        }
+      };
+      walk_list(list, a, a < N ? nblk[k] : 0, block);
+      const int nb = __builtin_amdgcn_readfirstlane((wave_max_i(cnt) + 7) >> 3);
+      fnb[k] = nb;
+      if (a < n_pad) {
+        const uint16_t pad = (uint16_t)(PB * (MI ? (a < N ? a : SENT) : SENT));
+        int q = cnt;
+        for (; (q & 7) && q < 8 * nb; ++q) ilist[(((q >> 3) * n_pad + a) << 3) + (q & 7)] = pad;
+        const uint32_t pp = (uint32_t)pad * 0x00010001u;
+        for (int b = q >> 3; b < nb; ++b) reinterpret_cast<uint4*>(ilist)[b * n_pad + a] = make_uint4(pp, pp, pp, pp);
+      }
+      prx[k] = xi;
+      pry[k] = yi;
+      prz[k] = zi;
+    }
+    inner = true;
+    __syncthreads();
   }
 
   template <int ACC, bool KAHAN>
@@ -749,7 +835,7 @@ struct Box {
       float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;  // Kahan sums and compensations
       float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;  // virial tensor
       int cin = 0;
-      const int nb = nblk[k];
+      const int nb = fnb[k];
       // one block of 8 list entries (two 16-bit byte offsets per word)
       auto block = [&](const uint4 ent) __attribute__((always_inline)) {
         const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
@@ -813,7 +899,7 @@ struct Box {
           }
         }
       };
-      walk_list(a, nb, block);
+      walk_list(force_list(), a, nb, block);
       fx[k] = ax;
       fy[k] = ay;
       fz[k] = az;
@@ -875,7 +961,7 @@ struct Box {
           rs += in ? fr : 0.0f;
         }
       };
-      walk_list(a, nblk[k], block);
+      walk_list(force_list(), a, fnb[k], block);
       const double rb = (double)rs;
       const double sq = rb > 0.0 ? sqrt(rb) : 0.0;
       fpi[k] = rb > 0.0 ? (float)(-eam_c / (2.0 * sq)) : 0.0f;
@@ -973,7 +1059,7 @@ struct Box {
           }
         }
       };
-      walk_list(a, nblk[k], block);
+      walk_list(force_list(), a, fnb[k], block);
       fx[k] = ax;
       fy[k] = ay;
       fz[k] = az;
@@ -1419,12 +1505,19 @@ struct Box {
     int pending = step + 1;  // first step not yet flushed
     pairs_t = 0.0;
     esteps = 0;
+    bool fresh = true;  // the first step of a launch prunes (the build before it left outer lists)
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+      prx[q] = (float)x[q];
+      pry[q] = (float)y[q];
+      prz[q] = (float)z[q];
+    }
     __syncthreads();
     bool stopped = ctl->stop != 0;
     while (step < target && !stopped) {
       const int k = step + 1;
-      // kick + drift, own ghosts, displacement since the build
-      float dm = 0.f;
+      // kick + drift, own ghosts, displacements since the build and the prune
+      float dm = 0.f, dp = 0.f;
       // Langevin noise amplitude of this step: beta has variance 2 gamma T dt
       const double hsig = nvt ? 0.5 * sqrt(gamma_dt2 * ctl->T_th) : 0.0;
 #pragma unroll
@@ -1450,6 +1543,10 @@ struct Box {
           }
           const float ex = (float)x[q] - bx[q], ey = (float)y[q] - by[q], ez = (float)z[q] - bz[q];
           dm = fmaxf(dm, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+          if (!LLDS && prune_cell) {
+            const float gx = (float)x[q] - prx[q], gy = (float)y[q] - pry[q], gz = (float)z[q] - prz[q];
+            dp = fmaxf(dp, fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+          }
         }
       }
       // owners write their atoms and ghost images (the last barrier of the
@@ -1457,11 +1554,20 @@ struct Box {
       refresh_positions();
       dm = wave_max(dm);
       if (lane == 0) ctl->wmax[wv] = dm;
+      if (!LLDS && prune_cell) {
+        dp = wave_max(dp);
+        if (lane == 0) ctl->pmax[wv] = dp;
+      }
       __syncthreads();
-      float gm = 0.f;
+      float gm = 0.f, gp = 0.f;
 #pragma unroll
       for (int w = 0; w < NW; ++w) gm = fmaxf(gm, ctl->wmax[w]);
-      if (gm > thr) {
+      if (!LLDS && prune_cell) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) gp = fmaxf(gp, ctl->pmax[w]);
+      }
+      const bool rebuilt = gm > thr;
+      if (rebuilt) {
         if (!rebuild()) {
           flush(pending, step);
           __syncthreads();
@@ -1471,6 +1577,10 @@ struct Box {
         }
         refresh_positions();
         __syncthreads();
+      }
+      if (!LLDS && prune_cell && (rebuilt || fresh || gp > pthr)) {
+        prune();
+        fresh = false;
       }
       const bool energy = is_energy_step(k);
       // steps where the stress tensor of Eq. stress is sampled (as <E_pot>)

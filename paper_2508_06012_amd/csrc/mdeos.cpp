@@ -290,7 +290,13 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     return MDEOS_INVALID_ARG;
   }
   eam_c = c_in > 0.0 ? c_in : 39.432;
-  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : (potential == MDEOS_POT_EAM ? 0.15f : 0.4f);
+  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : (potential == MDEOS_POT_EAM ? 0.5f : 0.4f);
+  const float ps_in = cfg ? cfg->prune_skin : 0.f;
+  if (!std::isfinite(ps_in)) {
+    set_error("prune_skin must be finite");
+    return MDEOS_INVALID_ARG;
+  }
+  prune_skin = ps_in > 0.f ? ps_in : (ps_in < 0.f ? 0.f : (potential == MDEOS_POT_EAM ? 0.12f : 0.f));
   hbm_budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : (size_t)64 << 30;
   autotune = cfg ? cfg->autotune : 0;
   if (cfg && cfg->tune_cache) tune_cache = cfg->tune_cache;
@@ -718,6 +724,10 @@ std::string Ctx::tune_key(const CellPlan& p) const {
   std::string key = buf;
   if (p.nvt) key += "/nvt";
   if (potential == MDEOS_POT_EAM) key += "/eam";
+  if (prune_lists()) {
+    snprintf(buf, sizeof(buf), "/prune%.3f", prune_skin);
+    key += buf;
+  }
   return key;
 }
 
@@ -806,8 +816,10 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
     b.work_off = (int)work_n;
     work_n += b.cells.size();
     if (!b.v.list_lds) {
+      // the lists of every workgroup, then (with pruning) their inner lists
       b.gl_off = gl_bytes;
-      gl_bytes += align_up((int)((size_t)b.grid * b.caps.list_cap * b.caps.n_pad * 2), 256);
+      const size_t one = (size_t)b.grid * b.caps.list_cap * b.caps.n_pad * 2;
+      gl_bytes += ((prune_lists() ? 2 : 1) * one + 255) / 256 * 256;
     }
   }
   mdeos_status st = ensure_scratch(work_n, kMaxBuckets, gl_bytes, 1);
@@ -917,6 +929,9 @@ AdvanceParams Ctx::make_params(const Bucket& b, int bi, int step_budget) {
   p.step_budget = step_budget;
   p.a = arena;
   p.gl_list = b.v.list_lds ? nullptr : d_gl + b.gl_off / 2;
+  p.gl_ilist = (b.v.list_lds || !prune_lists()) ? nullptr
+                                                 : p.gl_list + (size_t)b.grid * b.caps.list_cap * b.caps.n_pad;
+  p.prune_skin = prune_skin;
   p.caps = b.caps;
   p.kahan = precision == MDEOS_PREC_KAHAN ? 1 : 0;
   p.eam_c = eam_c;

@@ -107,6 +107,8 @@ struct AdvanceParams {
   int step_budget;      // steps per cell in this launch: 0 = to the end, < 0 = none (lift only)
   AtomArena a;
   uint16_t* gl_list;    // device-memory neighbour lists (per workgroup), or null
+  uint16_t* gl_ilist;   // device-memory inner (pruned) lists, same shape as gl_list, or null: no pruning
+  float prune_skin;     // the inner lists hold the entries within rc + prune_skin
   Caps caps;
   int kahan;            // 1: Kahan-compensated FP32 per-atom energy/virial sums, 0: FP64
   double eam_c;         // embedding strength of the embedded-atom variants

@@ -112,6 +112,10 @@ struct Ctx {
   int precision = MDEOS_PREC_FP64;
   int potential = MDEOS_POT_LJTS;  // material of every cell of the context
   double eam_c = 39.432;           // embedding strength of MDEOS_POT_EAM
+  float prune_skin = 0.f;          // inner-list skin (0: no inner lists)
+  // Inner lists are kept for lists in device memory; the compensated FP32
+  // sums would fold their zero terms differently, so that mode keeps none.
+  bool prune_lists() const { return prune_skin > 0.f && precision != MDEOS_PREC_KAHAN; }
   std::string arch = "gfx950";  // device architecture (tune-cache key)
   std::string tune_cache;
   std::recursive_mutex mu;

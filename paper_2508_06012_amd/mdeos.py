@@ -46,7 +46,7 @@ class Result(C.Structure):
 class Config(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget", C.c_size_t), ("skin", C.c_float), ("autotune", C.c_int),
                 ("tune_cache", C.c_char_p),
-                ("precision", C.c_int), ("potential", C.c_int), ("eam_c", C.c_double)]
+                ("precision", C.c_int), ("potential", C.c_int), ("eam_c", C.c_double), ("prune_skin", C.c_float)]
 
 
 class PlanInfo(C.Structure):
@@ -233,9 +233,9 @@ def mdeos_cell_bytes(n_c: int) -> int:
 
 def mdeos_create(device: int = 0, hbm_budget: int = 0, skin: float = 0.0, autotune: int = 0,
                  tune_cache: str | None = None, precision: int = 0, potential: int = 0,
-                 eam_c: float = 0.0) -> C.c_void_p:
+                 eam_c: float = 0.0, prune_skin: float = 0.0) -> C.c_void_p:
     cfg = Config(device, hbm_budget, skin, autotune, tune_cache.encode() if tune_cache else None, precision,
-                 potential, eam_c)
+                 potential, eam_c, prune_skin)
     ctx = C.c_void_p()
     _check(lib().mdeos_create(C.byref(cfg), C.byref(ctx)), "mdeos_create")
     return ctx

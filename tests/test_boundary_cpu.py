@@ -97,7 +97,9 @@ def test_create_rejects_unknown_precision():
 
 
 @pytest.mark.parametrize("kw,what", [({"potential": 2}, "potential"), ({"potential": 1, "eam_c": float("nan")},
-                                                                        "eam_c")])
+                                                                        "eam_c"),
+                                     ({"prune_skin": float("nan")}, "prune_skin"),
+                                     ({"prune_skin": float("inf")}, "prune_skin")])
 def test_create_rejects_an_unknown_potential(kw, what):
     # checked before any device call, so this runs on the CPU too
     with pytest.raises(m.MdeosError) as e:
@@ -107,15 +109,15 @@ def test_create_rejects_an_unknown_potential(kw, what):
 
 
 def test_eam_workload_cells_plan_into_eam_shapes():
-    """Every cell of the embedded-atom bench workload plans (at the EAM default
-    skin of 0.15, and at 0.25) with at most 4095 position slots, which the 4096-stride embedded-atom
-    shapes for 500-atom boxes hold (a shape serves any plan it covers)."""
+    """Every cell of the embedded-atom bench workload plans (at skins 0.15 and
+    0.25, and at the embedded-atom default of 0.5) with at most 4095 position slots, which the
+    4096-stride embedded-atom shapes for 500-atom boxes hold (a shape serves any plan it covers)."""
     from paper_2508_06012_amd import workloads as wl
     w = wl.eam_cu()
     assert w.potential == 1 and w.n == 4096 and set(w.N) == {500}
     assert 4.0 <= w.rho.min() and w.rho.max() <= 6.0
     specs, _ = m.specs_from_workload(w.subset(np.arange(0, 4096, 64)))
-    caps = [m.mdeos_plan(s, skin).ext_cap for s in specs for skin in (0.15, 0.25)]
+    caps = [m.mdeos_plan(s, skin).ext_cap for s in specs for skin in (0.15, 0.25, 0.5)]
     assert max(caps) < 4096, max(caps)
 
 

@@ -1,0 +1,72 @@
+"""Inner (pruned) neighbour lists give the same bits.
+
+Between list builds the force walks may use, instead of each atom's list at
+rc + skin, the entries within rc + s_in at the last prune, in list order. A
+prune follows whenever an atom has moved s_in / 2 since the previous one, so
+every pair that comes within rc is still walked, in the same order. Every
+entry dropped lies outside rc, where its terms are exact zeros. So a run
+with inner lists must equal, bit for bit, the run without them: every field
+of every result, for ghost-image and minimum-image boxes, both integrators and
+both potentials. Each case forces a launch shape whose lists live in device
+memory (inner lists exist only there) and compares pruning off, the default
+s_in and a small s_in that prunes nearly every step. The skins mix the
+defaults (one or few outer lists per run) with smaller ones (many).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2508_06012_amd import mdeos as m
+
+pytestmark = pytest.mark.gpu
+
+
+def run(shape, potential, skin, prune_skin, specs, sch):
+    os.environ["MDEOS_FORCE_VARIANT"] = ",".join(str(v) for v in shape)
+    try:
+        ctx = m.mdeos_create(potential=potential, skin=skin, prune_skin=prune_skin)
+    finally:
+        del os.environ["MDEOS_FORCE_VARIANT"]
+    try:
+        return m.mdeos_eval_batch(ctx, specs, sch)
+    finally:
+        m.mdeos_destroy(ctx)
+
+
+# (name, shape, potential, n_c, rho range, e range, rc, dt, ensemble, skin, inner skins)
+CASES = [
+    ("ljts-ghost", (512, 1, 4096, 0, 4, 0, 0, 0), 0, 5, (0.3, 1.1), (0.5, 3.0), 2.5, 0.004, 0, 0.8, (0.3, 0.04)),
+    ("ljts-ghost-langevin", (512, 1, 4096, 0, 2, 0, 1, 0), 0, 5, (0.3, 1.1), (0.5, 3.0), 2.5, 0.004, 1, 0.8,
+     (0.3, 0.04)),
+    ("ljts-minimum-image", (512, 8, 4088, 0, 1, 1, 0, 0), 0, 10, (0.3, 0.3), (1.0, 2.0), 2.5, 0.004, 0, 0.8,
+     (0.3, 0.04)),
+    ("eam-ghost", (512, 1, 4096, 0, 2, 0, 0, 1), 1, 5, (4.0, 6.0), (7.0, 35.0), 1.5, 0.001, 0, 0.5, (0.12, 0.02)),
+    ("eam-ghost-langevin", (512, 1, 4096, 0, 2, 0, 1, 1), 1, 5, (4.0, 6.0), (7.0, 35.0), 1.5, 0.001, 1, 0.3,
+     (0.12, 0.02)),
+    ("eam-minimum-image", (512, 8, 4088, 0, 1, 1, 0, 1), 1, 10, (4.0, 4.0), (10.0, 20.0), 1.5, 0.001, 0, 0.5,
+     (0.12, 0.02)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_inner_lists_give_the_same_bits(case):
+    name, shape, potential, n_c, rho, e, rc, dt, ensemble, skin, inner = case
+    n = 6
+    rng = np.random.default_rng(11)
+    specs = m.make_specs(rng.uniform(*rho, n), rng.uniform(*e, n), n_c, rc, dt, np.arange(20, 20 + n), np.arange(n))
+    # every cell fits the forced shape, so no cell falls back to a shape with its list in LDS
+    for sp in specs:
+        plan = m.mdeos_plan(sp, skin)
+        assert plan.ext_cap <= shape[2] - 1 and plan.N <= shape[0] * shape[1], (name, plan.ext_cap)
+        if shape[5]:
+            assert plan.ext_cap == 4087  # planned as a minimum-image box
+    sch = m.make_schedule(400, 200, (100, 200), 10, 10, ensemble=ensemble, gamma=1.0)
+    print(f"{name}: shape {shape}, {n} cells of {4 * n_c ** 3} atoms, skin {skin}, inner skins off / {inner}",
+          flush=True)
+    off = run(shape, potential, skin, -1.0, specs, sch)
+    assert not (off["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)).any()
+    print(f"  list builds per cell {off['n_builds'].tolist()}", flush=True)
+    for ps in inner:
+        got = run(shape, potential, skin, ps, specs, sch)
+        assert got.tobytes() == off.tobytes(), (name, ps)

@@ -30,10 +30,10 @@ def shape_table():
     return sorted(set(tuple(int(v) for v in t) for t in found))
 
 
-def run_forced(shape, potential, specs, sch):
+def run_forced(shape, potential, specs, sch, skin):
     os.environ["MDEOS_FORCE_VARIANT"] = ",".join(str(v) for v in shape)
     try:
-        ctx = m.mdeos_create(potential=potential)
+        ctx = m.mdeos_create(potential=potential, skin=skin)
     finally:
         del os.environ["MDEOS_FORCE_VARIANT"]
     try:
@@ -62,8 +62,8 @@ def test_every_launch_shape_gives_the_same_bits(name, potential, ensemble, state
               if v[5] == 0 and v[6] == ensemble and v[7] == potential and v[0] * v[1] >= N and v[2] - 1 >= plan.ext_cap]
     assert len(shapes) >= 3, shapes
     print(f"{name}: {len(shapes)} launch shapes", flush=True)
-    ref = run_forced(shapes[0], potential, specs, sch)
+    ref = run_forced(shapes[0], potential, specs, sch, skin)
     assert not (ref["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)).any()
     for v in shapes[1:]:
-        got = run_forced(v, potential, specs, sch)
+        got = run_forced(v, potential, specs, sch, skin)
         assert got.tobytes() == ref.tobytes(), v

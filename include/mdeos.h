@@ -130,12 +130,13 @@ typedef struct {
     int potential;             /* the material of every cell of the context: MDEOS_POT_LJTS (default)
                                   or MDEOS_POT_EAM */
     double eam_c;              /* embedding strength c of MDEOS_POT_EAM; <= 0 selects 39.432 */
-    float prune_skin;          /* inner-list skin s_in: between list builds, every time an atom has moved
-                                  s_in / 2 the force walks switch to the list entries within rc + s_in.
-                                  Results are bit-identical with and without (dropped entries add exact
-                                  zeros). 0 selects none (LJTS) or 0.12 (MDEOS_POT_EAM); < 0 turns
-                                  it off; no effect when s_in >= skin, for lists held in LDS, or with
-                                  MDEOS_PREC_KAHAN. NaN or infinity: MDEOS_INVALID_ARG. */
+    float prune_skin;          /* MDEOS_POT_EAM: inner-list skin s_in. Between list builds, every time
+                                  an atom has moved s_in / 2, the force walks switch to the list entries
+                                  within rc + s_in. Results are bit-identical with and without (dropped
+                                  entries add exact zeros). 0 selects 0.12; < 0 turns it off. No effect
+                                  when s_in >= skin, for lists held in LDS, with MDEOS_PREC_KAHAN, or for
+                                  MDEOS_POT_LJTS (whose shapes are built without inner lists).
+                                  NaN or infinity: MDEOS_INVALID_ARG. */
 } mdeos_config;
 
 /* Per-atom accumulation of pair energy and virial terms. The box sums that

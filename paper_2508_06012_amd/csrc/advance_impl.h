@@ -177,6 +177,9 @@ struct Box {
   static constexpr int SENT = EXT - 1;  // padding neighbour index
   using PT = typename std::conditional<MI, double, float>::type;  // LDS position type
   static constexpr int PB = sizeof(PT);
+  // inner lists (device-memory lists of the embedded-atom shapes only: its two
+  // walks per step are where they pay; the LJTS shapes carry none of their registers)
+  static constexpr bool PRUNE = !LLDS && EAM;
 
   const AdvanceParams& p;
   LdsLayout lay;
@@ -246,7 +249,7 @@ struct Box {
     px = (PT*)(lds + lay.pos);
     list = LLDS ? (uint16_t*)(lds + lay.list)
                 : p.gl_list + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
-    ilist = (LLDS || p.gl_ilist == nullptr || p.kahan != 0)
+    ilist = (!PRUNE || p.gl_ilist == nullptr || p.kahan != 0)
                 ? nullptr
                 : p.gl_ilist + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
     inner = false;
@@ -674,7 +677,7 @@ struct Box {
       cm = min(cm, list_cap);
       int nb = __builtin_amdgcn_readfirstlane((cm + 7) >> 3);
       nblk[k] = nb;
-      fnb[k] = nb;
+      if (PRUNE) fnb[k] = nb;
       // pad every lane of the wave (also atoms past N) to nb blocks: with the
       // far-away sentinel, or (minimum image, where no point is far from all
       // atoms) with the atom itself, which the r^2 > 0 test drops
@@ -741,7 +744,8 @@ struct Box {
   // byte offsets per word) to fn in order.
   // The list the force walks use: the inner lists after a prune, otherwise
   // the lists of the last build.
-  DEVI const uint16_t* force_list() const { return (!LLDS && inner) ? ilist : list; }
+  DEVI const uint16_t* force_list() const { return (PRUNE && inner) ? ilist : list; }
+  DEVI int force_blocks(int k) const { return PRUNE ? fnb[k] : nblk[k]; }
 
   template <class FN>
   DEVI void walk_list(const uint16_t* base, int a, int nb, FN&& fn) {
@@ -835,7 +839,7 @@ struct Box {
       float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;  // Kahan sums and compensations
       float sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;  // virial tensor
       int cin = 0;
-      const int nb = fnb[k];
+      const int nb = force_blocks(k);
       // one block of 8 list entries (two 16-bit byte offsets per word)
       auto block = [&](const uint4 ent) __attribute__((always_inline)) {
         const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
@@ -961,7 +965,7 @@ struct Box {
           rs += in ? fr : 0.0f;
         }
       };
-      walk_list(force_list(), a, fnb[k], block);
+      walk_list(force_list(), a, force_blocks(k), block);
       const double rb = (double)rs;
       const double sq = rb > 0.0 ? sqrt(rb) : 0.0;
       fpi[k] = rb > 0.0 ? (float)(-eam_c / (2.0 * sq)) : 0.0f;
@@ -1059,7 +1063,7 @@ struct Box {
           }
         }
       };
-      walk_list(force_list(), a, fnb[k], block);
+      walk_list(force_list(), a, force_blocks(k), block);
       fx[k] = ax;
       fy[k] = ay;
       fz[k] = az;
@@ -1506,11 +1510,13 @@ struct Box {
     pairs_t = 0.0;
     esteps = 0;
     bool fresh = true;  // the first step of a launch prunes (the build before it left outer lists)
+    if (PRUNE) {
 #pragma unroll
-    for (int q = 0; q < APT; ++q) {
-      prx[q] = (float)x[q];
-      pry[q] = (float)y[q];
-      prz[q] = (float)z[q];
+      for (int q = 0; q < APT; ++q) {
+        prx[q] = (float)x[q];
+        pry[q] = (float)y[q];
+        prz[q] = (float)z[q];
+      }
     }
     __syncthreads();
     bool stopped = ctl->stop != 0;
@@ -1543,7 +1549,7 @@ struct Box {
           }
           const float ex = (float)x[q] - bx[q], ey = (float)y[q] - by[q], ez = (float)z[q] - bz[q];
           dm = fmaxf(dm, fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
-          if (!LLDS && prune_cell) {
+          if (PRUNE && prune_cell) {
             const float gx = (float)x[q] - prx[q], gy = (float)y[q] - pry[q], gz = (float)z[q] - prz[q];
             dp = fmaxf(dp, fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
           }
@@ -1554,7 +1560,7 @@ struct Box {
       refresh_positions();
       dm = wave_max(dm);
       if (lane == 0) ctl->wmax[wv] = dm;
-      if (!LLDS && prune_cell) {
+      if (PRUNE && prune_cell) {
         dp = wave_max(dp);
         if (lane == 0) ctl->pmax[wv] = dp;
       }
@@ -1562,7 +1568,7 @@ struct Box {
       float gm = 0.f, gp = 0.f;
 #pragma unroll
       for (int w = 0; w < NW; ++w) gm = fmaxf(gm, ctl->wmax[w]);
-      if (!LLDS && prune_cell) {
+      if (PRUNE && prune_cell) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) gp = fmaxf(gp, ctl->pmax[w]);
       }
@@ -1578,7 +1584,7 @@ struct Box {
         refresh_positions();
         __syncthreads();
       }
-      if (!LLDS && prune_cell && (rebuilt || fresh || gp > pthr)) {
+      if (PRUNE && prune_cell && (rebuilt || fresh || gp > pthr)) {
         prune();
         fresh = false;
       }

@@ -296,7 +296,7 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     set_error("prune_skin must be finite");
     return MDEOS_INVALID_ARG;
   }
-  prune_skin = ps_in > 0.f ? ps_in : (ps_in < 0.f ? 0.f : (potential == MDEOS_POT_EAM ? 0.12f : 0.f));
+  prune_skin = ps_in > 0.f ? ps_in : (ps_in < 0.f ? 0.f : 0.12f);
   hbm_budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : (size_t)64 << 30;
   autotune = cfg ? cfg->autotune : 0;
   if (cfg && cfg->tune_cache) tune_cache = cfg->tune_cache;

@@ -113,9 +113,12 @@ struct Ctx {
   int potential = MDEOS_POT_LJTS;  // material of every cell of the context
   double eam_c = 39.432;           // embedding strength of MDEOS_POT_EAM
   float prune_skin = 0.f;          // inner-list skin (0: no inner lists)
-  // Inner lists are kept for lists in device memory; the compensated FP32
-  // sums would fold their zero terms differently, so that mode keeps none.
-  bool prune_lists() const { return prune_skin > 0.f && precision != MDEOS_PREC_KAHAN; }
+  // Inner lists are kept for the device-memory lists of the embedded-atom
+  // shapes only; the compensated FP32 sums would fold their zero terms
+  // differently, so that mode keeps none.
+  bool prune_lists() const {
+    return prune_skin > 0.f && precision != MDEOS_PREC_KAHAN && potential == MDEOS_POT_EAM;
+  }
   std::string arch = "gfx950";  // device architecture (tune-cache key)
   std::string tune_cache;
   std::recursive_mutex mu;

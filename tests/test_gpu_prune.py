@@ -1,16 +1,16 @@
 """Inner (pruned) neighbour lists give the same bits.
 
-Between list builds the force walks may use, instead of each atom's list at
-rc + skin, the entries within rc + s_in at the last prune, in list order. A
-prune follows whenever an atom has moved s_in / 2 since the previous one, so
-every pair that comes within rc is still walked, in the same order. Every
-entry dropped lies outside rc, where its terms are exact zeros. So a run
-with inner lists must equal, bit for bit, the run without them: every field
-of every result, for ghost-image and minimum-image boxes, both integrators and
-both potentials. Each case forces a launch shape whose lists live in device
+Between list builds the embedded-atom force walks may use, instead of each
+atom's list at rc + skin, the entries within rc + s_in at the last prune, in
+list order. A prune follows whenever an atom has moved s_in / 2 since the
+previous one, so every pair that comes within rc is still walked, in the same
+order. Every entry dropped lies outside rc, where its terms are exact zeros.
+So a run with inner lists must equal, bit for bit, the run without them:
+every field of every result, for ghost-image and minimum-image boxes and both
+integrators. Each case forces a launch shape whose lists live in device
 memory (inner lists exist only there) and compares pruning off, the default
 s_in and a small s_in that prunes nearly every step. The skins mix the
-defaults (one or few outer lists per run) with smaller ones (many).
+default (one or few outer lists per run) with a smaller one (many).
 """
 import os
 
@@ -36,13 +36,10 @@ def run(shape, potential, skin, prune_skin, specs, sch):
 
 # (name, shape, potential, n_c, rho range, e range, rc, dt, ensemble, skin, inner skins)
 CASES = [
-    ("ljts-ghost", (512, 1, 4096, 0, 4, 0, 0, 0), 0, 5, (0.3, 1.1), (0.5, 3.0), 2.5, 0.004, 0, 0.8, (0.3, 0.04)),
-    ("ljts-ghost-langevin", (512, 1, 4096, 0, 2, 0, 1, 0), 0, 5, (0.3, 1.1), (0.5, 3.0), 2.5, 0.004, 1, 0.8,
-     (0.3, 0.04)),
-    ("ljts-minimum-image", (512, 8, 4088, 0, 1, 1, 0, 0), 0, 10, (0.3, 0.3), (1.0, 2.0), 2.5, 0.004, 0, 0.8,
-     (0.3, 0.04)),
     ("eam-ghost", (512, 1, 4096, 0, 2, 0, 0, 1), 1, 5, (4.0, 6.0), (7.0, 35.0), 1.5, 0.001, 0, 0.5, (0.12, 0.02)),
     ("eam-ghost-langevin", (512, 1, 4096, 0, 2, 0, 1, 1), 1, 5, (4.0, 6.0), (7.0, 35.0), 1.5, 0.001, 1, 0.3,
+     (0.12, 0.02)),
+    ("eam-ghost-small-skin", (512, 1, 4096, 0, 2, 0, 0, 1), 1, 5, (4.0, 6.0), (7.0, 35.0), 1.5, 0.001, 0, 0.3,
      (0.12, 0.02)),
     ("eam-minimum-image", (512, 8, 4088, 0, 1, 1, 0, 1), 1, 10, (4.0, 4.0), (10.0, 20.0), 1.5, 0.001, 0, 0.5,
      (0.12, 0.02)),

@@ -122,7 +122,8 @@ typedef struct {
 typedef struct {
     int device;                /* HIP device ordinal */
     size_t hbm_budget;         /* bytes of resident cell state the context may hold; 0 = 64 GiB */
-    float skin;                /* Verlet skin; <= 0 selects 0.4 (LJTS) or 0.5 (MDEOS_POT_EAM) */
+    float skin;                /* Verlet skin; <= 0 selects, per cell, 0.4 (LJTS), or for MDEOS_POT_EAM
+                                  0.5 up to 1000 atoms and 0.3 above */
     int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
     const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
     int precision;             /* how each atom sums its pair energies and virials (forces are FP32):

@@ -290,7 +290,7 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     return MDEOS_INVALID_ARG;
   }
   eam_c = c_in > 0.0 ? c_in : 39.432;
-  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : (potential == MDEOS_POT_EAM ? 0.5f : 0.4f);
+  skin = (cfg && cfg->skin > 0.f) ? cfg->skin : 0.f;  // 0: per cell (cell_skin)
   const float ps_in = cfg ? cfg->prune_skin : 0.f;
   if (!std::isfinite(ps_in)) {
     set_error("prune_skin must be finite");
@@ -524,7 +524,7 @@ mdeos_status Ctx::alloc_cells(int n, const mdeos_cell_spec* specs, const mdeos_s
   for (int i = 0; i < n; ++i) {
     mdeos_status st = mdeos_validate(&specs[i], &q);
     if (st != MDEOS_OK) return st;
-    st = plan_cell(specs[i], skin, plans[i]);
+    st = plan_cell(specs[i], cell_skin(specs[i]), plans[i]);
     plans[i].nvt = q.ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;
     if (st != MDEOS_OK) {
       set_error("cell " + std::to_string(i) + ": box too large for an LDS-resident extended box");
@@ -1094,7 +1094,7 @@ extern "C" mdeos_status mdeos_warm_start(mdeos_ctx* ctx, int n, const mdeos_hand
     sp.seed = r.seed;
     sp.cell_id = r.cell_id;
     CellPlan p;
-    mdeos_status st = plan_cell(sp, c->skin, p);
+    mdeos_status st = plan_cell(sp, c->cell_skin(sp), p);
     if (st != MDEOS_OK) return set_error("warm target too large"), st;
     p.nvt = sched->ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;
     const double Lold = r.Lw;

@@ -105,7 +105,7 @@ struct ServeCell {
 struct Ctx {
   int device = 0;
   int n_cu = 256;
-  float skin = 0.3f;
+  float skin = 0.f;  // Verlet skin set by the caller, or 0: the default of cell_skin
   size_t hbm_budget = 0;
   int autotune = 0;
   int tune_runs = 0;  // buckets timed by the autotuner so far
@@ -116,6 +116,15 @@ struct Ctx {
   // Inner lists are kept for the device-memory lists of the embedded-atom
   // shapes only; the compensated FP32 sums would fold their zero terms
   // differently, so that mode keeps none.
+  // Verlet skin of a cell: the caller's, else the measured best of the
+  // potential. 0.4 sigma for LJTS. For the embedded-atom form: 0.5 a up to 1000
+  // atoms, and 0.3 a above, where the ghost-extended boxes at 0.5 outgrow their
+  // launch shapes.
+  float cell_skin(const mdeos_cell_spec& s) const {
+    if (skin > 0.f) return skin;
+    if (potential != MDEOS_POT_EAM) return 0.4f;
+    return 4L * s.n_c * s.n_c * s.n_c <= 1000 ? 0.5f : 0.3f;
+  }
   bool prune_lists() const {
     return prune_skin > 0.f && precision != MDEOS_PREC_KAHAN && potential == MDEOS_POT_EAM;
   }

@@ -121,7 +121,7 @@ extern "C" mdeos_status mdeos_serve_submit(mdeos_ctx* ctx, long long cell_id, do
   mdeos_cell_spec sp{rho, e, n_c, c->serve_cfg.rc, c->serve_cfg.dt, c->serve_cfg.seed, cell_id};
   if (mdeos_validate(&sp, nullptr) != MDEOS_OK) return MDEOS_INVALID_ARG;
   CellPlan p;
-  if (plan_cell(sp, c->skin, p) != MDEOS_OK) return MDEOS_INVALID_ARG;
+  if (plan_cell(sp, c->cell_skin(sp), p) != MDEOS_OK) return MDEOS_INVALID_ARG;
   std::lock_guard<std::mutex> lk(c->serve_mu);
   if (!c->serving || c->serve_stop_flag) return MDEOS_NOT_READY;
   ServeQuery q{c->next_ticket++, cell_id, rho, e, n_c, t_arrival};
@@ -242,7 +242,7 @@ void Ctx::serve_loop() {
       const ServeQuery q = *it;
       mdeos_cell_spec sp{q.rho, q.e, q.n_c, cfg.rc, cfg.dt, cfg.seed, q.cell_id};
       CellPlan p;
-      const mdeos_status pst = plan_cell(sp, skin, p);
+      const mdeos_status pst = plan_cell(sp, cell_skin(sp), p);
       p.nvt = cfg.warm.ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;  // used by warm starts (cold ones re-plan)
       if (pst != MDEOS_OK) {
         ServeDone d{q.ticket, {}, mono_now() - serve_t0};

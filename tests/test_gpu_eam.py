@@ -72,7 +72,7 @@ def test_forces_on_oracle_positions(ctx, cell):
 def test_forces_minimum_image_4000(ctx):
     """A box too large for ghost images in LDS: the minimum-image variant."""
     cell = ecell(4.0, 20.0, 10, cell_id=5)
-    plan = m.mdeos_plan(gspec(cell), 0.5)  # the default embedded-atom skin
+    plan = m.mdeos_plan(gspec(cell), 0.3)  # the default embedded-atom skin above 1000 atoms
     assert plan.ext_cap == 4087  # the minimum-image plan: real atoms only
     rng = np.random.default_rng(3)
     L = oracle.box_length(cell.n_c, cell.rho)
@@ -234,7 +234,7 @@ def test_langevin_minimum_image_4000_first_20_steps(ctx):
     (4000 atoms, minimum image): 20 GJF steps with a temperature update at
     step 10, per step against the oracle."""
     cell = ecell(4.0, 14.0, 10, cell_id=9)
-    assert m.mdeos_plan(gspec(cell), 0.5).ext_cap == 4087
+    assert m.mdeos_plan(gspec(cell), 0.3).ext_cap == 4087
     n = 20
     x0, v0, Ec = oracle.lift(cell)
     ref = oracle.run(cell, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(10,), energy_every=5,

@@ -67,3 +67,29 @@ def test_inner_lists_give_the_same_bits(case):
     for ps in inner:
         got = run(shape, potential, skin, ps, specs, sch)
         assert got.tobytes() == off.tobytes(), (name, ps)
+
+
+def test_mixed_sizes_at_the_default_skins():
+    """The default embedded-atom skin is chosen per cell (0.5 up to 1000 atoms,
+    0.3 above), so one batch holds buckets planned at different skins, all with
+    inner lists. Every cell of such a batch is bitwise equal to itself run
+    alone, and to the same cell run with inner lists off."""
+    rng = np.random.default_rng(12)
+    n_c = np.array([5, 8, 5, 8, 6, 5])
+    n = len(n_c)
+    specs = m.make_specs(rng.uniform(4.0, 6.0, n), rng.uniform(7.0, 35.0, n), n_c, 1.5, 0.001,
+                         np.arange(40, 40 + n), np.arange(n))
+    sch = m.make_schedule(300, 150, (75, 150), 10, 10)
+    print(f"mixed embedded-atom batch: {(4 * n_c ** 3).tolist()} atoms at the default skins", flush=True)
+    ctx = m.mdeos_create(potential=m.POT_EAM)
+    off = m.mdeos_create(potential=m.POT_EAM, prune_skin=-1.0)
+    try:
+        batch = m.mdeos_eval_batch(ctx, specs, sch)
+        assert not (batch["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)).any()
+        assert batch.tobytes() == m.mdeos_eval_batch(off, specs, sch).tobytes()
+        for i in range(n):
+            alone = m.mdeos_eval_batch(ctx, (m.CellSpec * 1)(specs[i]), sch)[0]
+            assert alone.tobytes() == batch[i].tobytes(), i
+    finally:
+        m.mdeos_destroy(ctx)
+        m.mdeos_destroy(off)

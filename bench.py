@@ -49,6 +49,7 @@ FLOP_PAIR_EAM = 48         # embedded-atom form: density walk 17 + force and vir
 FLOP_PAIR_EAM_ENERGY = 7   # extra on energy steps (the pair energy)
 HERE = os.path.dirname(os.path.abspath(__file__))
 ADVANCE = "k_advance"      # the dominant kernel (name prefix in traces)
+SERVE_LEGS = ((2000.0, 2), (10000.0, 4), (50000.0, 10))  # (queries/s, continuum steps)
 PROFILE_NAME = {"cfg2": "uniform_4096x500", "cfg3": "uneven_10000", "cfg5": "large_65536x864",
                 "eam": "eam_4096x500"}
 
@@ -96,6 +97,34 @@ def _oracle_job(args):
     return r.P, r.P_se, r.T, r.T_se, r.status
 
 
+def _cfg1_job(_):
+    import oracle
+    from paper_2508_06012_amd import workloads as wl
+    w = wl.cfg1()
+    cell = oracle.Cell(rho=float(w.rho[0]), e=float(w.e[0]), n_c=int(w.n_c[0]), rc=float(w.rc[0]),
+                       dt=float(w.dt[0]), seed=int(w.seed), cell_id=int(w.cell_id[0]))
+    s = w.sched
+    t0 = time.perf_counter()
+    oracle.run(cell, oracle.Schedule(s.n_steps, s.n_avg, rescale_steps=tuple(s.rescale_steps)))
+    return time.perf_counter() - t0
+
+
+def cfg1_oracle_rates(wl, workers):
+    """The single 256-atom cell (1000 steps) through the oracle: on one core,
+    and as one copy per core on `workers` cores at once (evals/s)."""
+    import multiprocessing as mp
+
+    import oracle
+    oracle.build()
+    one = _cfg1_job(0)
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        pool.map(_cfg1_job, range(workers), chunksize=1)
+        wall = time.perf_counter() - t0
+    return {"one_core_s_per_eval": round(one, 4), "one_core_evals_per_s": round(1.0 / one, 4),
+            "all_cores_evals_per_s": round(workers / wall, 4), "all_cores": workers}
+
+
 def cpu_baseline(w, idx, gpu_res, workers):
     """The oracle as it stands on a stratified sample, parallel over cells."""
     import multiprocessing as mp
@@ -119,7 +148,11 @@ def cpu_baseline(w, idx, gpu_res, workers):
 
 
 def serve_leg(m, wl, rate: float, mesh: int, t_steps: int, seconds_cap: float):
-    """A short serving run: Poisson queries from a drifting field, cold then warm."""
+    """Serving run of the cfg4 stream: Poisson queries from a drifting field
+    over a mesh x mesh grid of cells, the first visit of each cell a cold lift
+    of 2000 steps and later visits warm starts of 500 steps, for the first
+    t_steps continuum steps (submissions stop after seconds_cap; every
+    submitted query is drained). Latency = result visible to poll - arrival."""
     ctx = m.mdeos_create()
     queries, meta = wl.cfg4_queries(rate, mesh=mesh, t_max=t_steps)
     cold, warm = meta["cold"], meta["warm"]
@@ -130,8 +163,9 @@ def serve_leg(m, wl, rate: float, mesh: int, t_steps: int, seconds_cap: float):
     kinds = {}
     t0 = m.mdeos_serve_now(ctx)
     seen = set()
-    done = []
-    for q in queries:
+    max_queued = max_active = 0
+    max_resident_bytes = 0
+    for i, q in enumerate(queries):
         t_target = t0 + q.t_arrival
         while m.mdeos_serve_now(ctx) < t_target:
             time.sleep(min(0.0005, max(0.0, t_target - m.mdeos_serve_now(ctx))))
@@ -139,10 +173,16 @@ def serve_leg(m, wl, rate: float, mesh: int, t_steps: int, seconds_cap: float):
         arrival[tk] = m.mdeos_serve_now(ctx)
         kinds[tk] = "warm" if q.cell in seen else "cold"
         seen.add(q.cell)
+        if i % 512 == 0:
+            st = m.mdeos_serve_stats_get(ctx)
+            max_queued = max(max_queued, st["queued"])
+            max_active = max(max_active, st["active"])
+            max_resident_bytes = max(max_resident_bytes, st["resident_bytes"])
         if m.mdeos_serve_now(ctx) - t0 > seconds_cap:
             break
+    t_submit = m.mdeos_serve_now(ctx) - t0
     m.mdeos_serve_stop(ctx, drain=True)
-    tickets, res, td = m.mdeos_serve_poll(ctx, 1 << 20)
+    tickets, res, td = m.mdeos_serve_poll(ctx, 1 << 22)
     stats = m.mdeos_serve_stats_get(ctx)
     wall = m.mdeos_serve_now(ctx) - t0
     m.mdeos_destroy(ctx)
@@ -150,16 +190,45 @@ def serve_leg(m, wl, rate: float, mesh: int, t_steps: int, seconds_cap: float):
     for tk, t in zip(tickets, td):
         lat[kinds[int(tk)]].append(t - arrival[int(tk)])
     out = {"rate_qps": rate, "queries": int(len(tickets)), "mesh": mesh, "continuum_steps": t_steps,
+           "submit_s": round(t_submit, 3), "wall_s": round(wall, 3),
            "evals_per_s": len(tickets) / wall, "atom_steps_per_s": stats["atom_steps"] / wall,
-           "relifts": stats["relifts"], "failed": int((res["status"] & (1 | 8)).astype(bool).sum())}
+           "cold": int(stats["cold"]), "warm": int(stats["warm"]), "relifts": int(stats["relifts"]),
+           "chunks": int(stats["chunks"]), "max_queue_depth": int(max_queued), "max_in_flight": int(max_active),
+           "resident_bytes": int(max(max_resident_bytes, stats["resident_bytes"])),
+           "failed": int((res["status"] & (1 | 8)).astype(bool).sum())}
     for k in ("cold", "warm"):
         a = np.array(lat[k])
         if a.size:
-            out[f"{k}_p50_ms"] = float(np.percentile(a, 50) * 1e3)
-            out[f"{k}_p99_ms"] = float(np.percentile(a, 99) * 1e3)
+            out[f"{k}_p50_ms"] = round(float(np.percentile(a, 50) * 1e3), 3)
+            out[f"{k}_p99_ms"] = round(float(np.percentile(a, 99) * 1e3), 3)
     allv = np.array(lat["cold"] + lat["warm"])
-    out["p50_ms"] = float(np.percentile(allv, 50) * 1e3)
-    out["p99_ms"] = float(np.percentile(allv, 99) * 1e3)
+    out["p50_ms"] = round(float(np.percentile(allv, 50) * 1e3), 3)
+    out["p99_ms"] = round(float(np.percentile(allv, 99) * 1e3), 3)
+    return out
+
+
+def plain_latency(m, wl):
+    """Per-eval latency of the plain path (one cell per launch) for the
+    serving stream's cell sizes: a fresh lift + the cold schedule (2000
+    steps), and a fresh lift + the warm schedule's 500 steps."""
+    _, meta = wl.cfg4_queries(1000.0, mesh=2, t_max=1)
+    cold, warm = meta["cold"], meta["warm"]
+    ctx = m.mdeos_create()
+    out = {}
+    try:
+        for N, n_c in ((256, 4), (500, 5), (864, 6)):
+            spec = m.make_specs(0.8, float(wl.e_from_T(1.5, N)), n_c, meta["rc"], meta["dt"], wl.DEFAULT_SEED, 0)
+            for name, s in (("cold", m.make_schedule(cold.n_steps, cold.n_avg, cold.rescale_steps)),
+                            ("warm_steps", m.make_schedule(warm.n_steps, warm.n_avg, ()))):
+                m.mdeos_eval_plain(ctx, spec, s)
+                lat = []
+                for _ in range(3):
+                    t1 = time.perf_counter()
+                    m.mdeos_eval_plain(ctx, spec, s)
+                    lat.append(time.perf_counter() - t1)
+                out[f"N{N}_{name}_ms"] = round(float(np.median(lat)) * 1e3, 3)
+    finally:
+        m.mdeos_destroy(ctx)
     return out
 
 
@@ -276,7 +345,6 @@ def main() -> int:
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=10000.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="end with one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
@@ -405,17 +473,27 @@ def main() -> int:
                        "T_se": float(r1["T_se"][0])}
     m.mdeos_destroy(ctx)
     if default and not args.no_serve:
-        print("# serving leg", file=sys.stderr, flush=True)
-        out["serving"] = serve_leg(m, wl, args.serve_rate, mesh=32, t_steps=6, seconds_cap=30.0)
+        # the serving stream at its full mesh, three rates, each over a prefix
+        # of continuum steps (step 0 is every cell's cold lift)
+        legs = []
+        for rate, t_steps in SERVE_LEGS:
+            print(f"# serving leg: 128 x 128 mesh, {rate:.0f} queries/s, {t_steps} continuum steps", file=sys.stderr,
+                  flush=True)
+            legs.append(serve_leg(m, wl, rate, mesh=128, t_steps=t_steps, seconds_cap=25.0))
+            print(f"#   {json.dumps(legs[-1])}", file=sys.stderr, flush=True)
+        out["serving"] = {"workload": "cfg4-serving-128x128", "legs": legs, "plain_latency": plain_latency(m, wl)}
     if default and not args.no_cpu:
-        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        affinity = len(os.sched_getaffinity(0))
+        workers = args.cpu_workers or min(16, affinity)
         cidx = np.linspace(0, n - 1, args.cpu_sample).astype(int)
         print(f"# cpu baseline: oracle on {len(cidx)} cells with {workers} processes", file=sys.stderr, flush=True)
         cwall, wp, wt = cpu_baseline(w, cidx, res, workers)
+        c1 = cfg1_oracle_rates(wl, workers)
         out["cpu_baseline"] = {"value": round(len(cidx) / cwall, 4), "unit": "EOS evals/s", "cores": workers,
                                "kind": "oracle",
                                "sample": f"{len(cidx)} stratified cells of {w.name}, full 2000-step schedule, "
-                                         f"{cwall:.1f} s wall, one cell per process"}
+                                         f"{cwall:.1f} s wall, one cell per process",
+                               "host_cpu_count": os.cpu_count(), "affinity_cpus": affinity, "cfg1": c1}
         out["parity"] = {"cells": int(len(cidx)), "P_within_3_combined_se": int(wp), "T_within_3_combined_se": int(wt)}
     if args.copy_mib > 0:
         # a plain device copy of known size, last on the device (counter calibration)

@@ -106,7 +106,7 @@ typedef struct {
     double T_se;       /* block standard error of <T> */
     double Epot_mean;  /* <E_pot> / N over energy steps in the window */
     double Ecold;      /* E_cold / N of the static lattice at rho */
-    double drift;      /* (E(n) - E(n - n_avg)) / N */
+    double drift;      /* (E(n) - E(n - n_avg)) / N; NaN before step n */
     double pairs;      /* ordered pairs within rc per step, averaged over energy steps */
     int n_samples;     /* samples averaged */
     int status;        /* MDEOS_CELL_* bits */
@@ -219,19 +219,33 @@ mdeos_status mdeos_lift_from_state(mdeos_ctx* ctx, const mdeos_cell_spec* spec, 
 mdeos_status mdeos_warm_start(mdeos_ctx* ctx, int n, const mdeos_handle* h, const double* rho, const double* e,
                               const mdeos_schedule* sched, void* stream);
 
-/* Advances each cell by up to n_steps MD steps (velocity Verlet or GJF, as
- * its schedule's ensemble says; never past the schedule's end), in one
- * persistent launch per size bucket. */
+/* Microscopic model (Sec. II.B): advances each cell by up to n_steps MD steps
+ * (velocity Verlet, or the GJF Langevin integrator the paper cites, as its
+ * schedule's ensemble says; never past the schedule's end), with the
+ * temperature updates of Eq. Tcontribution (Sec. III) at the schedule's
+ * steps, in one persistent launch per size bucket. h[n] are handles of
+ * resident cells (MDEOS_INVALID_ARG for a stale or unknown handle).
+ * n_steps = 0 runs only a pending lift or warm-start phase; n_steps < 0 is
+ * MDEOS_INVALID_ARG. Asynchronous on the stream. */
 mdeos_status mdeos_advance(mdeos_ctx* ctx, int n, const mdeos_handle* h, int n_steps, void* stream);
 
-/* Restricting operator: writes one result per handle (blocks on the stream).
- * Cells that have not reached the end of their schedule get MDEOS_NOT_READY
- * as the call status and their partial averages. */
+/* Restricting operator (Sec. III, Eq. stress): writes one result per handle
+ * into out[n] (host memory; blocks on the stream). Cells that have not
+ * reached the end of their schedule make the call return MDEOS_NOT_READY;
+ * their results hold the averages of the window samples recorded so far
+ * (n_samples of them), block errors over the completed blocks only (NaN with
+ * fewer than two) and a NaN drift. */
 mdeos_status mdeos_restrict(mdeos_ctx* ctx, int n, const mdeos_handle* h, mdeos_result* out, void* stream);
 
-/* lift + full schedule + restrict for n cells: one persistent launch per size
- * bucket, replayed from a cached HIP graph for repeated batch shapes. The
- * cells are released afterwards. */
+/* One equation-of-state evaluation per spec, the equation-free coupling of
+ * Sec. III (lifting, microscopic model of Sec. II.B, restriction): lift +
+ * full schedule + restrict for n cells, with one persistent launch per size
+ * bucket, replayed from a cached HIP graph for repeated batch shapes.
+ * specs[n] and out[n] are host arrays read / written during the call; the
+ * call blocks until out is written. Per-cell failures are status bits of
+ * out[i]; invalid specs or schedules fail the whole call with
+ * MDEOS_INVALID_ARG before any device work. The cells are released
+ * afterwards. */
 mdeos_status mdeos_eval_batch(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched,
                               mdeos_result* out, void* stream);
 

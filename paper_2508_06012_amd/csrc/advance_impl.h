@@ -502,9 +502,12 @@ struct Box {
     for (int i = 0; i < n; ++i) fpv[g + i] = v;
   }
 
+  // Binning cell of a coordinate, clamped to the grid. Written so that no
+  // value, NaN and infinities included, reaches a float-to-int conversion
+  // out of its range: NaN and negative values land in cell 0.
   DEVI int cell_coord(float v) const {
-    int q = (int)floorf((MI ? v : v + rl) * inv_ce);
-    return min(max(q, 0), nce - 1);
+    const float u = (MI ? v : v + rl) * inv_ce;
+    return u >= 1.0f ? min((int)fminf(u, (float)nce), nce - 1) : 0;
   }
   DEVI int wrapc(int q) const { return q < 0 ? q + nce : (q >= nce ? q - nce : q); }
   // nearest periodic image of a coordinate difference (FP64 positions)
@@ -615,7 +618,11 @@ struct Box {
             if (d2[u] < rl2 && e4[u] != a) push((uint32_t)(PB * e4[u]));
         }
       };
-      if (a < N && MI) {
+      // an atom whose position is not finite (a blown-up cell, which the
+      // step's observables flag) gets an empty list: the stencil bounds below
+      // convert coordinates to integers
+      const bool fin = isfinite(bx[k]) && isfinite(by[k]) && isfinite(bz[k]);
+      if (a < N && MI && fin) {
         // periodic stencil, one cell at a time (the grid has at least 2R+1
         // cells per edge); rows and cells the rl-sphere cannot reach are
         // skipped (see the ghost branch)
@@ -640,7 +647,7 @@ struct Box {
             }
           }
         }
-      } else if (a < N) {
+      } else if (a < N && fin) {
         // Rows (dy, dz) of the stencil in fixed order. In cell units (u = the
         // atom's fractional cell coordinate) a row is skipped when its y and z
         // cell intervals are at least rl away, and its x range is cut to the

@@ -19,38 +19,50 @@ MDEOS_VARIANTS(X)
 namespace {
 
 // Restricting operator: time averages and block standard errors (FP64).
+// A cell still inside its averaging window gets the averages of the samples
+// recorded so far and block errors over its completed blocks only (NaN with
+// fewer than two); its drift is NaN until the window's last step.
 __global__ void k_restrict(const CellRec* cells, const int* idx, int n, DevResult* out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const CellRec& c = cells[idx[i]];
   DevResult r;
+  const bool fin = c.phase == PH_DONE;
   const int B = c.n_blocks, na = c.n_avg, bl = na / B;
-  const int done = (c.phase == PH_DONE) ? c.n_avg : max(0, c.step - (c.n_steps - c.n_avg));
+  const int done = fin ? na : min(na, max(0, c.step - (c.n_steps - na)));
+  const int Bc = fin ? B : min(B, done / bl);  // completed blocks
   double sP = 0.0, sT = 0.0;
   for (int b = 0; b < B; ++b) {
     sP += c.sumP[b];
     sT += c.sumT[b];
   }
-  r.P = sP / na;
-  r.T = sT / na;
+  r.P = done > 0 ? sP / done : NAN;
+  r.T = done > 0 ? sT / done : NAN;
+  double cP = 0.0, cT = 0.0;
+  for (int b = 0; b < Bc; ++b) {
+    cP += c.sumP[b];
+    cT += c.sumT[b];
+  }
+  const double mP = cP / ((double)Bc * bl), mT = cT / ((double)Bc * bl);
   double aP = 0.0, aT = 0.0;
-  for (int b = 0; b < B; ++b) {
-    const double mp = c.sumP[b] / bl - r.P, mt = c.sumT[b] / bl - r.T;
+  for (int b = 0; b < Bc; ++b) {
+    const double mp = c.sumP[b] / bl - mP, mt = c.sumT[b] / bl - mT;
     aP += mp * mp;
     aT += mt * mt;
   }
-  r.P_se = sqrt(aP / (B * (B - 1.0)));
-  r.T_se = sqrt(aT / (B * (B - 1.0)));
+  r.P_se = Bc >= 2 ? sqrt(aP / (Bc * (Bc - 1.0))) : NAN;
+  r.T_se = Bc >= 2 ? sqrt(aT / (Bc * (Bc - 1.0))) : NAN;
+  // one pass about the window's first sample: var = <(P - P_ref)^2> - (<P> - P_ref)^2
   const double d = r.P - c.P_ref;
-  const double var = c.sumdP2 / na - d * d;
-  r.P_rms = sqrt(var > 0.0 ? var : 0.0);
+  const double var = c.sumdP2 / done - d * d;
+  r.P_rms = done > 0 ? sqrt(var > 0.0 ? var : 0.0) : NAN;
   r.Epot_mean = c.nU > 0 ? c.sumU / c.nU / c.N : NAN;
   r.Ecold = c.Ecold / c.N;
-  r.drift = (c.E_n - c.E_w0) / c.N;
+  r.drift = fin ? (c.E_n - c.E_w0) / c.N : NAN;
   // Eq. stress: (kinetic + pair virial) / V averaged over the sampled steps
   for (int q = 0; q < 6; ++q) r.stress[q] = c.nS > 0 ? (c.sigK[q] + c.sigV[q]) / (c.nS * c.V) : NAN;
   int st = c.status;
-  if (c.ensemble != MDEOS_NVT_LANGEVIN && fabs(r.drift) > c.drift_tol) st |= ST_DRIFT;  // energy is not conserved under a thermostat
+  if (fin && c.ensemble != MDEOS_NVT_LANGEVIN && fabs(r.drift) > c.drift_tol) st |= ST_DRIFT;  // energy is not conserved under a thermostat
   if (st & (ST_NONFINITE | ST_OVERFLOW)) {
     r.P = r.P_se = r.P_rms = r.T = r.T_se = r.Epot_mean = r.drift = NAN;
     for (int q = 0; q < 6; ++q) r.stress[q] = NAN;

@@ -329,6 +329,7 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     return MDEOS_DEVICE_ERROR;
   }
   load_tune_cache();
+  if (const char* sc = getenv("MDEOS_SHRINK_CAPS")) shrink_caps = atoi(sc) != 0;
   if (const char* fv = getenv("MDEOS_FORCE_VARIANT")) {
     Variant v{};
     const int nf = sscanf(fv, "%d,%d,%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi,
@@ -1154,6 +1155,17 @@ mdeos_status Ctx::eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule
   std::vector<int> idx;
   mdeos_status st = alloc_cells(n, specs, *sched, idx);
   if (st != MDEOS_OK) return st;
+  if (shrink_caps) {
+    for (int slot : idx) {
+      CellPlan p = cell_plan[slot];
+      p.list_cap = 8;
+      if (finish_plan(p) != MDEOS_OK) continue;
+      const CellRec old = h_cells[slot];
+      mdeos_cell_spec sp{old.rho, old.e, old.n_c, old.rc, old.dt, old.seed, old.cell_id};
+      fill_record(h_cells[slot], sp, *sched, p, old.atom_off);
+      cell_plan[slot] = p;
+    }
+  }
   std::vector<int> pos(n);
   for (int i = 0; i < n; ++i) pos[i] = i;
   std::vector<int> todo = idx;
@@ -1184,11 +1196,19 @@ mdeos_status Ctx::eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule
       if (!(res[i].status & MDEOS_CELL_OVERFLOW) || attempt == 2) continue;
       const int slot = todo[i];
       CellPlan p = cell_plan[slot];
-      p.ext_need = std::max(p.ext_need + p.ext_need / 2, res[i].max_ext + 64);
-      p.list_cap = align_up(std::max(p.list_cap + p.list_cap / 2, res[i].max_list + 16), 8);
-      if (finish_plan(p) != MDEOS_OK) continue;  // no larger launch shape: report the overflow
       const CellRec old = h_cells[slot];
       mdeos_cell_spec sp{old.rho, old.e, old.n_c, old.rc, old.dt, old.seed, old.cell_id};
+      // grow by half, to the sizes the overflow measured plus a margin, and
+      // never below what a fresh plan of the cell gives
+      CellPlan fresh;
+      const bool have_fresh = plan_cell(sp, cell_skin(sp), fresh) == MDEOS_OK && fresh.minimg == p.minimg;
+      p.ext_need = std::max(p.ext_need + p.ext_need / 2, res[i].max_ext + 64);
+      p.list_cap = align_up(std::max(p.list_cap + p.list_cap / 2, res[i].max_list + 16), 8);
+      if (have_fresh) {
+        p.ext_need = std::max(p.ext_need, fresh.ext_need);
+        p.list_cap = std::max(p.list_cap, fresh.list_cap);
+      }
+      if (finish_plan(p) != MDEOS_OK) continue;  // no larger launch shape: report the overflow
       fill_record(h_cells[slot], sp, *sched, p, old.atom_off);
       cell_plan[slot] = p;
       again.push_back(slot);

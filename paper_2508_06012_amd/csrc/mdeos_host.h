@@ -170,6 +170,11 @@ struct Ctx {
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, Variant> tuned;
   Variant forced_variant{0, 0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe,mi" (tuning)
+  // MDEOS_SHRINK_CAPS=1: eval_batch / eval_plain plan every cell with an
+  // 8-entry neighbour list, so the first list build overflows and their
+  // capacity retry runs (a test hook: capacities never change a cell's
+  // arithmetic, so the retried results equal an unforced run bit for bit)
+  bool shrink_caps = false;
 
   // serving
   std::thread serve_thread;

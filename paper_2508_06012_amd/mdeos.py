@@ -93,13 +93,37 @@ class MdeosError(RuntimeError):
 _lib = None
 
 
+def hip_runtimes() -> set:
+    """Paths of the HIP runtime libraries (libamdhip64) mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(line.split()[-1])
+    except OSError:
+        pass
+    return paths
+
+
 def lib() -> C.CDLL:
-    """Loads libmdeos.so; raises if it was not built (no fallback)."""
+    """Loads libmdeos.so; raises if it was not built (no fallback).
+
+    One HIP runtime per process: PyTorch ships its own copy of the HIP runtime
+    under the same soname as the system's. When torch is importable it is
+    imported first, so the library binds to that copy and torch streams, torch
+    memory and the library's work share one runtime. Loaded the other way
+    round, the process maps both runtimes, each with its own device state and
+    hardware queues, and a torch stream is foreign to the library."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_06012_amd.build`")
+    try:
+        import torch  # noqa: F401  (maps torch's HIP runtime before the library resolves its own)
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     vp = C.c_void_p
@@ -147,6 +171,10 @@ def _stream(stream) -> C.c_void_p:
     if stream is None:
         return None
     if hasattr(stream, "cuda_stream"):
+        rt = hip_runtimes()
+        if len(rt) > 1:
+            raise MdeosError(INVALID_ARG, "a torch stream with two HIP runtimes mapped (" + ", ".join(sorted(rt)) +
+                             "): import torch before loading libmdeos.so, so both use one runtime")
         return C.c_void_p(int(stream.cuda_stream))
     return C.c_void_p(int(stream))
 

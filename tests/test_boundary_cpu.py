@@ -146,3 +146,35 @@ def test_validate_ensemble_and_friction(ensemble, gamma, ok):
     sch = m.make_schedule(100, 50, (10,), ensemble=ensemble, gamma=gamma)
     st = m.lib().mdeos_validate(C.byref(spec), C.byref(sch))
     assert (st == m.OK) == ok
+
+
+GUARD_CHILD = r"""
+import ctypes, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2508_06012_amd import mdeos as m
+ctypes.CDLL(m.LIB_PATH)  # the library first: it maps the system HIP runtime
+import torch  # then torch maps its own copy
+class S:
+    cuda_stream = 0
+print("runtimes", len(m.hip_runtimes()))
+try:
+    m._stream(S())
+    print("accepted")
+except m.MdeosError as e:
+    print("refused:", e)
+"""
+
+
+def test_torch_stream_refused_under_two_hip_runtimes():
+    """A process that loaded the library before torch maps two HIP runtimes;
+    the binding then refuses a torch stream instead of handing the library a
+    handle of the other runtime (checked in a child process, no device)."""
+    pytest.importorskip("torch")
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", GUARD_CHILD, root], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    if "runtimes 1" in r.stdout:
+        pytest.skip("torch resolved the library's runtime: one runtime mapped")
+    assert "runtimes 2" in r.stdout and "refused: " in r.stdout, r.stdout

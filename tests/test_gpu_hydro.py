@@ -21,6 +21,8 @@ import time
 import numpy as np
 import pytest
 
+import oracle
+from _stats import check_stats, oracle_many
 from paper_2508_06012_amd import mdeos as m
 from paper_2508_06012_amd.hydro import MDEOS, Lagrangian1D, MieGruneisen
 
@@ -108,6 +110,28 @@ def ctx():
     m.mdeos_destroy(c)
 
 
+def test_driver_device_calls_match_the_oracle(ctx):
+    """The cold curve E_cold/N per zone (the energy-zero conversion of every
+    call, C25) against the oracle's static-lattice energy to the energy bar;
+    the first call's fresh lifts (lift, 1000-step schedule with re-pins,
+    restriction) against oracle runs of the same specs (same Philox key per
+    zone, same energy above cold) by the statistical bar."""
+    nz = 8
+    eos = MDEOS(nz, n_c=4, rc=2.5, dt=0.004, seed=3, ctx=ctx)
+    rho = np.linspace(0.55, 1.05, nz)
+    print(f"driver vs oracle: cold curve and first lifts of {nz} zones", flush=True)
+    ec = eos.cold_curve(rho)
+    want = np.array([oracle.ecold(4, float(r), 2.5) / 256 for r in rho])
+    assert np.all(np.abs(ec - want) <= 1e-6 * np.abs(want)), (ec, want)
+    p = eos(rho, want + np.linspace(1.0, 3.0, nz))
+    assert eos.failed == 0 and np.array_equal(p, eos.last["P"])
+    cells = [oracle.Cell(rho=float(rho[i]), e=float(eos.e_md[i]), n_c=4, rc=2.5, dt=0.004, seed=3, cell_id=i)
+             for i in range(nz)]
+    o = oracle_many(cells, 1000, 500, (250, 500))
+    check_stats(list(eos.last), o, "driver first lifts", [f"zone {i} rho {rho[i]:.3f}" for i in range(nz)])
+    eos.close()
+
+
 def test_piston_into_lj_fluid_with_the_md_eos(ctx):
     print(f"piston into LJ fluid: {N_ZONES} zones, rho1 {RHO1}, e1 {E_MD1} above cold, up {UP}", flush=True)
     eos = MDEOS(N_ZONES, n_c=4, rc=2.5, dt=0.004, seed=3, ctx=ctx)
@@ -137,11 +161,9 @@ def test_piston_into_lj_fluid_with_the_md_eos(ctx):
 
 
 def test_piston_into_eam_copper():
-    """The same problem in the embedded-atom stand-in for copper, the paper's
-    application material (reduced units: a = 3.6153 A, eps = 0.012382 eV):
-    the fitted lattice (rho 4.0 per a^3), e 3.0 above the cold lattice (T about
-    e / 3 for a harmonic crystal, about 150 K), a piston at 7.3 a/tau (about
-    1 km/s)."""
+    """The same problem in the embedded-atom stand-in for the paper's
+    application material: the fitted lattice (rho 4.0 per a^3), e 3.0 above
+    the cold lattice, a piston at 7.3 a/tau."""
     rho1, e_md1, up = 4.0, 3.0, 7.3
     ctx = m.mdeos_create(potential=m.POT_EAM)
     try:

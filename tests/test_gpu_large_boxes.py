@@ -1,0 +1,92 @@
+"""Per-step parity of the 1372- and 2048-atom boxes (about 43 % of the
+uneven batch's atom-steps) against the FP64 oracle, in every image mode these
+sizes take at the uneven batch's densities and cutoffs: ghost-extended boxes
+with 4096 or 8176 position slots, and minimum-image boxes. The paper's own boxes run
+from O(10^3) to 4000 atoms (App. C).
+
+Bars as in test_gpu_parity: forces 1e-5 norm-wise and, per atom, 1e-4 of
+max(|F_i|, RMS per-atom force); energies 1e-6 of max(|E_pot|, K).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06012_amd import mdeos as m
+from paper_2508_06012_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SKIN = 0.4  # the library's LJTS default
+
+
+def _mode(cell):
+    """Image mode of the cell's plan; the plan reports the usable position
+    slots (the stride minus the padding slot), 4087 for minimum image."""
+    p = m.mdeos_plan(m.make_specs(cell.rho, cell.e, cell.n_c, cell.rc, cell.dt, cell.seed, cell.cell_id)[0], SKIN)
+    return "minimum-image" if p.ext_cap == 4087 else f"ghost-{p.ext_cap + 1}"
+
+
+# one cell per (size, image mode) of the uneven batch: of its 1372-atom boxes,
+# 1036 are ghost boxes of 8176 slots and 167 (the dilute ones) of 4096; of its
+# 2048-atom boxes, 1334 are ghost boxes of 8176 slots and 183 (dense, rc 3.0)
+# minimum-image boxes. The expected mode is asserted, so a planner change that
+# moves a case to another kernel shows up here.
+CASES = [
+    (oracle.Cell(rho=1.1, e=float(wl.e_from_T(2.0, 1372)), n_c=7, rc=2.5, dt=0.004, seed=3, cell_id=21), "ghost-8176"),
+    (oracle.Cell(rho=0.25, e=float(wl.e_from_T(3.0, 1372)), n_c=7, rc=2.5, dt=0.004, seed=3, cell_id=22),
+     "ghost-4096"),
+    (oracle.Cell(rho=0.6, e=float(wl.e_from_T(4.0, 2048)), n_c=8, rc=2.5, dt=0.004, seed=3, cell_id=23), "ghost-8176"),
+    (oracle.Cell(rho=1.1, e=float(wl.e_from_T(1.5, 2048)), n_c=8, rc=3.0, dt=0.004, seed=3, cell_id=24),
+     "minimum-image"),
+]
+IDS = [f"N{c.N}-rho{c.rho}-rc{c.rc}-{mode}" for c, mode in CASES]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = m.mdeos_create()
+    yield c
+    m.mdeos_destroy(c)
+
+
+def _atom_err(F, F0, scale):
+    """Per-atom force error over max(|F0_i|, RMS per-atom force), as in test_gpu_parity."""
+    floor = scale / np.sqrt(len(F0))
+    return (np.linalg.norm(F - F0, axis=1) / np.maximum(np.linalg.norm(F0, axis=1), floor)).max()
+
+
+@pytest.mark.parametrize("cell,mode", CASES, ids=IDS)
+def test_large_box_forces_and_steps(ctx, cell, mode):
+    assert _mode(cell) == mode
+    spec = m.make_specs(cell.rho, cell.e, cell.n_c, cell.rc, cell.dt, cell.seed, cell.cell_id)[0]
+    L = oracle.box_length(cell.n_c, cell.rho)
+    x0, v0, Ec = oracle.lift(cell)
+    # kernel parity on a disordered configuration
+    rng = np.random.default_rng(cell.cell_id)
+    x = x0 + rng.normal(scale=0.08, size=x0.shape)
+    x = (x - L * np.floor(x / L)).astype(np.float32).astype(np.float64)
+    F0, U0, W0 = oracle.forces(x, L, cell.rc)
+    print(f"large box {cell.N} {mode}: forces", flush=True)
+    F, U, W = m.mdeos_debug_forces(ctx, spec, x)
+    assert np.linalg.norm(F - F0) / np.linalg.norm(F0) <= 1e-5
+    assert _atom_err(F, F0, np.linalg.norm(F0)) <= 1e-4
+    assert abs(U - U0) <= 1e-6 * abs(U0)
+    assert abs(W - W0) <= 1e-5 * max(abs(W0), abs(U0))
+    # 30 free-running steps from the lifted bits, with a re-pin at step 15
+    n = 30
+    ref = oracle.run(cell, oracle.Schedule(n_steps=n, n_avg=10, n_blocks=2, rescale_steps=(15,), energy_every=1),
+                     x=x0, v=v0, Ecold_total=Ec, n_recF=n + 1)
+    print(f"large box {cell.N} {mode}: {n} steps", flush=True)
+    h = m.mdeos_lift_from_state(ctx, spec, m.make_schedule(100, 50, (15,), 10, 1), x0, v0)
+    Fg, K, Ug, _ = m.mdeos_debug_trajectory(ctx, h, n, cell.N)
+    m.mdeos_release(ctx, [h])
+    scale = np.linalg.norm(ref.F[-1])
+    ferr = [np.linalg.norm(Fg[k] - ref.F[k]) / max(np.linalg.norm(ref.F[k]), scale) for k in range(n + 1)]
+    aerr = [_atom_err(Fg[k], ref.F[k], max(np.linalg.norm(ref.F[k]), scale)) for k in range(n + 1)]
+    den = np.maximum(np.abs(ref.U), ref.K)
+    uerr, kerr = np.abs(Ug - ref.U) / den, np.abs(K - ref.K) / den
+    print(f"  max rel err: F {max(ferr):.2e} per atom {max(aerr):.2e} U {uerr.max():.2e} K {kerr.max():.2e}",
+          flush=True)
+    print("  force error per step: " + " ".join(f"{e:.1e}" for e in ferr), flush=True)
+    assert max(ferr) <= 1e-5 and max(aerr) <= 1e-4
+    assert uerr.max() <= 1e-6 and kerr.max() <= 1e-6

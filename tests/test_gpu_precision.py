@@ -22,7 +22,7 @@ import pytest
 import oracle
 from paper_2508_06012_amd import mdeos as m
 from paper_2508_06012_amd import workloads as wl
-from test_gpu_workloads import check_stats
+from _stats import check_stats
 
 pytestmark = pytest.mark.gpu
 

@@ -149,3 +149,43 @@ def test_warm_start_below_cold_relifts():
         m.mdeos_release(ctx, h)
     finally:
         m.mdeos_destroy(ctx)
+
+
+def test_staggered_arrivals_equal_alone_bitwise():
+    """Continuous batching proper: queries arrive one by one while chunks of
+    earlier queries run on the device. Each submission records whether cells
+    were in flight at that moment; most must have been. Every result is
+    bitwise equal to the cell's query sequence run alone."""
+    ctx = m.mdeos_create()
+    try:
+        qs = queries(n_cells=8, per_cell=3, seed=7)
+        rng = np.random.default_rng(2)
+        print(f"staggered serving of {len(qs)} queries", flush=True)
+        m.mdeos_serve_start(ctx, sched(COLD), sched(WARM), RC, DT, SEED, chunk_steps=25)
+        tickets, busy, got = [], 0, {}
+        for c, rho, e, n_c in qs:
+            busy += 1 if m.mdeos_serve_stats_get(ctx)["active"] > 0 else 0
+            tickets.append(m.mdeos_serve_submit(ctx, c, rho, e, n_c, m.mdeos_serve_now(ctx)))
+            time.sleep(float(rng.uniform(0.0, 0.004)))
+            tk, res, _ = m.mdeos_serve_poll(ctx, 1024)
+            got.update({int(k): r for k, r in zip(tk, res)})
+        t0 = time.time()
+        while len(got) < len(qs) and time.time() - t0 < 90.0:
+            tk, res, _ = m.mdeos_serve_poll(ctx, 1024)
+            got.update({int(k): r for k, r in zip(tk, res)})
+            time.sleep(0.01)
+        stats = m.mdeos_serve_stats_get(ctx)
+        m.mdeos_serve_stop(ctx, drain=True)
+        print(f"  submitted while cells were in flight: {busy} of {len(qs)}; chunks {stats['chunks']}", flush=True)
+        assert len(got) == len(qs), (len(got), stats)
+        assert busy >= len(qs) // 2, busy
+        for c in range(8):
+            seq = [q for q in qs if q[0] == c]
+            tk = [t for t, q in zip(tickets, qs) if q[0] == c]
+            ref = alone(ctx, c, seq)
+            for k in range(len(seq)):
+                r = got[tk[k]]
+                assert r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) == 0
+                assert r.tobytes() == ref[k].tobytes(), (c, k)
+    finally:
+        m.mdeos_destroy(ctx)

@@ -51,6 +51,36 @@ def test_stress_matches_oracle_from_identical_bits(ctx, cell, ens):
     err = np.abs(sg - so) / scale
     print(f"  oracle {np.round(so, 5)}\n  gpu    {np.round(sg, 5)}\n  max err / scale {err.max():.2e}", flush=True)
     assert err.max() <= 1e-5, err
+    check_restriction(g, ref, cell, na)
+
+
+def check_restriction(g, ref, cell, n_avg):
+    """Every restricted field against the oracle's, from identical starting
+    bits (trajectories equal to ~1e-7 over these steps). Pressure-like fields
+    (virial moments, force bar 1e-5) are scaled by max(|<P>|, rho <T>);
+    energy-like fields (energy bar 1e-6), <T> among them (2 <K> / N_DOF), by
+    the per-atom energy scale max(|<E_pot>|/N, <T>), the per-atom form of the
+    per-step bar max(|E_pot|, K); the drift is a difference of two total
+    energies, each held to the energy bar."""
+    pscale = max(abs(ref.P), cell.rho * ref.T)
+    escale = max(abs(ref.Epot_mean), ref.T)
+    errs = {
+        "P": abs(g["P"] - ref.P) / pscale,
+        "P_se": abs(g["P_se"] - ref.P_se) / pscale,
+        "P_rms": abs(g["P_rms"] - ref.P_rms) / pscale,
+        "T": abs(g["T"] - ref.T) / escale,
+        "T_se": abs(g["T_se"] - ref.T_se) / escale,
+        "Epot_mean": abs(g["Epot_mean"] - ref.Epot_mean) / escale,
+        "Ecold": abs(g["Ecold"] - ref.Ecold) / abs(ref.Ecold),
+        "drift": abs(g["drift"] - ref.drift) / (2 * escale),
+    }
+    print("  restricted fields, error / scale: " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+    for k in ("P", "P_se", "P_rms"):
+        assert errs[k] <= 1e-5, (k, g[k], getattr(ref, k))
+    for k in ("T", "T_se", "Epot_mean", "Ecold", "drift"):
+        assert errs[k] <= 1e-6, (k, g[k], getattr(ref, k))
+    assert g["n_samples"] == n_avg == ref.n_samples
+    assert g["status"] == ref.status
 
 
 def test_trace_over_three_is_the_pressure(ctx):

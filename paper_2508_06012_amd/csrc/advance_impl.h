@@ -180,6 +180,15 @@ struct Box {
   // inner lists (device-memory lists of the embedded-atom shapes only: its two
   // walks per step are where they pay; the LJTS shapes carry none of their registers)
   static constexpr bool PRUNE = !LLDS && EAM;
+  // Cell-sorted position slots (ghost-image LJTS shapes): a list build places
+  // every atom and image at its slot in cell order (cells in index order,
+  // each cell's members by extended index), keeps the extended-index -> slot
+  // map in `sorted`, and lists name slots. A row of the binning stencil is
+  // then a run of consecutive slots, read without an index load. The walk
+  // visits the same neighbours in the same order as with positions by
+  // extended index, so the bits do not change. (The embedded-atom shapes keep
+  // F'(rhobar) where the map would live; minimum-image boxes hold no images.)
+  static constexpr bool SORTED = !MI && !EAM;
 
   const AdvanceParams& p;
   LdsLayout lay;
@@ -239,6 +248,7 @@ struct Box {
   double wi[APT], ui[APT];
   float sv[6][APT];  // per-atom pair virial tensor of a sampled step (xx, yy, zz, xy, xz, yz)
   int gofs[APT], gmask[APT], nblk[APT], cnt_in[APT];
+  int sslot[APT];  // slot of each owned atom (SORTED)
   int fnb[APT];                      // blocks of the list the force walks use (wave-uniform)
   float prx[APT], pry[APT], prz[APT];  // positions at the last prune
   double pairs_t;  // ordered in-range pairs of this thread's atoms over sampled steps
@@ -494,6 +504,41 @@ struct Box {
     }
   }
 
+  // Calls fn(X, Y, Z, i) for the periodic images of one atom in the order
+  // write_images stores them (i = 0, 1, ...), with the same FP32 coordinates.
+  template <class FN>
+  DEVI void for_images(double xx, double yy, double zz, int m, FN&& fn) const {
+    const int nfx = (m >> 1) & 1, nfy = (m >> 3) & 1, nfz = (m >> 5) & 1;
+    const int nx = 1 + (m & 1) + nfx, ny = 1 + ((m >> 2) & 1) + nfy, nz = 1 + ((m >> 4) & 1) + nfz;
+    int i = 0;
+#pragma unroll 1
+    for (int ix = 0; ix < nx; ++ix) {
+      const int sx = ix - nfx;
+      const float X = (float)(xx + sx * Lw);
+#pragma unroll 1
+      for (int iy = 0; iy < ny; ++iy) {
+        const int sy = iy - nfy;
+        const float Y = (float)(yy + sy * Lw);
+#pragma unroll 1
+        for (int iz = 0; iz < nz; ++iz) {
+          const int sz = iz - nfz;
+          if ((sx | sy | sz) == 0) continue;
+          fn(X, Y, (float)(zz + sz * Lw), i);
+          ++i;
+        }
+      }
+    }
+  }
+  // Current images of one atom into their sorted slots (SORTED).
+  DEVI void write_images_sorted(double xx, double yy, double zz, int m, int g) {
+    for_images(xx, yy, zz, m, [&](float X, float Y, float Z, int i) __attribute__((always_inline)) {
+      const int sl = sorted[g + i];
+      PX(sl) = X;
+      PY(sl) = Y;
+      PZ(sl) = Z;
+    });
+  }
+
   // F'(rhobar) of one atom into its ghost slots g .. g + n_images(m) - 1
   // (the slots write_images fills for the same mask).
   DEVI void write_image_vals(float v, int m, int g) {
@@ -512,9 +557,10 @@ struct Box {
   DEVI int wrapc(int q) const { return q < 0 ? q + nce : (q >= nce ? q - nce : q); }
   // nearest periodic image of a coordinate difference (FP64 positions)
   DEVI double mimg(double d) const { return fma(-Lw, rint(d * invLw), d); }
-  DEVI int cell_of(int e) {
-    return (cell_coord((float)PZ(e)) * nce + cell_coord((float)PY(e))) * nce + cell_coord((float)PX(e));
+  DEVI int cell_xyz(float X, float Y, float Z) const {
+    return (cell_coord(Z) * nce + cell_coord(Y)) * nce + cell_coord(X);
   }
+  DEVI int cell_of(int e) { return cell_xyz((float)PX(e), (float)PY(e), (float)PZ(e)); }
 
   // Builds ghosts, the binning and every atom's neighbour list from the
   // build positions (bx, by, bz). Returns false on a capacity overflow.
@@ -525,9 +571,11 @@ struct Box {
       int a = t + k * BLOCK;
       gmask[k] = 0;
       if (a < N) {
-        PX(a) = bx[k];
-        PY(a) = by[k];
-        PZ(a) = bz[k];
+        if (!SORTED) {
+          PX(a) = bx[k];
+          PY(a) = by[k];
+          PZ(a) = bz[k];
+        }
         if (!MI) {
           gmask[k] = ghost_mask(bx[k], by[k], bz[k]);
           scanbuf[a] = n_images(gmask[k]);
@@ -541,39 +589,110 @@ struct Box {
       if (t == 0) atomicMax(&c->max_ext, n_ext);
       return false;
     }
+    if constexpr (SORTED) {
+      // Every atom and its images, enumerated by their owner: cell counts,
+      // placement, then the rank inside the cell by extended index, which
+      // gives the slot; the position goes there and the slot into `sorted`.
+      // (scanbuf, read here, shares tmp..sorted: both are written only after
+      // the barriers below.)
 #pragma unroll
-    for (int k = 0; k < APT; ++k) {
-      int a = t + k * BLOCK;
-      if (a < N && !MI) {
-        gofs[k] = N + scanbuf[a];
-        write_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k], gofs[k]);
+      for (int k = 0; k < APT; ++k) {
+        const int a = t + k * BLOCK;
+        sslot[k] = SENT;
+        if (a < N) gofs[k] = N + scanbuf[a];
       }
+      for (int q = t; q < ncell; q += BLOCK) {
+        cstart[q] = 0;
+        cfill[q] = 0;
+      }
+      if (t == 0) cstart[ncell] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        if (!valid(k)) continue;
+        atomicAdd(&cstart[cell_xyz(bx[k], by[k], bz[k])], 1);
+        if (gmask[k])
+          for_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k],
+                     [&](float X, float Y, float Z, int) __attribute__((always_inline)) {
+                       atomicAdd(&cstart[cell_xyz(X, Y, Z)], 1);
+                     });
+      }
+      __syncthreads();
+      block_scan(cstart, ncell + 1);
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        if (!valid(k)) continue;
+        const int a = t + k * BLOCK;
+        auto place = [&](float X, float Y, float Z, int e) __attribute__((always_inline)) {
+          const int cq = cell_xyz(X, Y, Z);
+          tmp[cstart[cq] + atomicAdd(&cfill[cq], 1)] = (uint16_t)e;
+        };
+        place(bx[k], by[k], bz[k], a);
+        if (gmask[k])
+          for_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k],
+                     [&](float X, float Y, float Z, int i) __attribute__((always_inline)) {
+                       place(X, Y, Z, gofs[k] + i);
+                     });
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        if (!valid(k)) continue;
+        const int a = t + k * BLOCK;
+        auto settle = [&](float X, float Y, float Z, int e) __attribute__((always_inline)) {
+          const int cq = cell_xyz(X, Y, Z);
+          const int lo = cstart[cq], hi = cstart[cq + 1];
+          int r = 0;
+          for (int q = lo; q < hi; ++q) r += (tmp[q] < e) ? 1 : 0;
+          PX(lo + r) = X;
+          PY(lo + r) = Y;
+          PZ(lo + r) = Z;
+          sorted[e] = (uint16_t)(lo + r);
+          return lo + r;
+        };
+        sslot[k] = settle(bx[k], by[k], bz[k], a);
+        if (gmask[k])
+          for_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k],
+                     [&](float X, float Y, float Z, int i) __attribute__((always_inline)) {
+                       settle(X, Y, Z, gofs[k] + i);
+                     });
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int k = 0; k < APT; ++k) {
+        int a = t + k * BLOCK;
+        if (a < N && !MI) {
+          gofs[k] = N + scanbuf[a];
+          write_images((double)bx[k], (double)by[k], (double)bz[k], gmask[k], gofs[k]);
+        }
+      }
+      for (int q = t; q < ncell; q += BLOCK) {
+        cstart[q] = 0;
+        cfill[q] = 0;
+      }
+      if (t == 0) cstart[ncell] = 0;
+      __syncthreads();
+      // bin every extended atom
+      for (int e = t; e < n_ext; e += BLOCK) atomicAdd(&cstart[cell_of(e)], 1);
+      __syncthreads();
+      block_scan(cstart, ncell + 1);
+      for (int e = t; e < n_ext; e += BLOCK) {
+        int cq = cell_of(e);
+        int s = atomicAdd(&cfill[cq], 1);
+        tmp[cstart[cq] + s] = (uint16_t)e;
+      }
+      __syncthreads();
+      // stable order inside each cell: rank by extended index
+      for (int e = t; e < n_ext; e += BLOCK) {
+        int cq = cell_of(e);
+        int lo = cstart[cq], hi = cstart[cq + 1];
+        int r = 0;
+        for (int q = lo; q < hi; ++q) r += (tmp[q] < e) ? 1 : 0;
+        sorted[lo + r] = (uint16_t)e;
+      }
+      __syncthreads();
     }
-    for (int q = t; q < ncell; q += BLOCK) {
-      cstart[q] = 0;
-      cfill[q] = 0;
-    }
-    if (t == 0) cstart[ncell] = 0;
-    __syncthreads();
-    // bin every extended atom
-    for (int e = t; e < n_ext; e += BLOCK) atomicAdd(&cstart[cell_of(e)], 1);
-    __syncthreads();
-    block_scan(cstart, ncell + 1);
-    for (int e = t; e < n_ext; e += BLOCK) {
-      int cq = cell_of(e);
-      int s = atomicAdd(&cfill[cq], 1);
-      tmp[cstart[cq] + s] = (uint16_t)e;
-    }
-    __syncthreads();
-    // stable order inside each cell: rank by extended index
-    for (int e = t; e < n_ext; e += BLOCK) {
-      int cq = cell_of(e);
-      int lo = cstart[cq], hi = cstart[cq + 1];
-      int r = 0;
-      for (int q = lo; q < hi; ++q) r += (tmp[q] < e) ? 1 : 0;
-      sorted[lo + r] = (uint16_t)e;
-    }
-    __syncthreads();
     // neighbour lists: rows of the (2R+1)^3 stencil in fixed order
     int over = 0;
 #pragma unroll
@@ -584,19 +703,26 @@ struct Box {
         if (cnt < list_cap) list[(((cnt >> 3) * n_pad + a) << 3) + (cnt & 7)] = (uint16_t)v;
         ++cnt;
       };
-      // Appends the atoms sorted[lo..hi) within rl of the build position of
-      // atom a, in order. Four candidates per round: their indices and
-      // positions are all loaded before the first is tested, so the LDS
-      // latency of the dependent loads is paid once per four. Slots past hi
-      // point at the atom itself, which the e != a test drops.
+      // Appends the atoms in cell order lo..hi within rl of the build
+      // position of atom a, in order. Four candidates per round: their
+      // positions (and, without sorted slots, their indices first) are all
+      // loaded before the first is tested, so the LDS latency is paid once
+      // per four. Entries past hi point at the atom itself, which the
+      // self test drops. Pushed values are position offsets: slots when
+      // SORTED, extended indices otherwise.
       const float bxi = bx[k], byi = by[k], bzi = bz[k];
+      const int self = SORTED ? sslot[k] : a;
       auto scan = [&](int lo, int hi) __attribute__((always_inline)) {
         for (int q = lo; q < hi; q += 4) {
           int e4[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int e = sorted[min(q + u, hi - 1)];
-            e4[u] = q + u < hi ? e : a;
+            if (SORTED) {
+              e4[u] = q + u < hi ? q + u : self;
+            } else {
+              const int e = sorted[min(q + u, hi - 1)];
+              e4[u] = q + u < hi ? e : a;
+            }
           }
           float d2[4];
 #pragma unroll
@@ -615,7 +741,7 @@ struct Box {
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (d2[u] < rl2 && e4[u] != a) push((uint32_t)(PB * e4[u]));
+            if (d2[u] < rl2 && e4[u] != self) push((uint32_t)(PB * e4[u]));
         }
       };
       // an atom whose position is not finite (a blown-up cell, which the
@@ -713,10 +839,16 @@ struct Box {
     for (int k = 0; k < APT; ++k) {
       int a = t + k * BLOCK;
       if (a < N) {
-        PX(a) = (PT)x[k];
-        PY(a) = (PT)y[k];
-        PZ(a) = (PT)z[k];
-        if (gmask[k]) write_images(x[k], y[k], z[k], gmask[k], gofs[k]);
+        const int sl = SORTED ? sslot[k] : a;
+        PX(sl) = (PT)x[k];
+        PY(sl) = (PT)y[k];
+        PZ(sl) = (PT)z[k];
+        if (gmask[k]) {
+          if (SORTED)
+            write_images_sorted(x[k], y[k], z[k], gmask[k], gofs[k]);
+          else
+            write_images(x[k], y[k], z[k], gmask[k], gofs[k]);
+        }
       }
     }
   }

@@ -254,6 +254,31 @@ mdeos_status mdeos_eval_batch(mdeos_ctx* ctx, int n, const mdeos_cell_spec* spec
 mdeos_status mdeos_eval_plain(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched,
                               mdeos_result* out, void* stream);
 
+/* For callers that cannot allocate memory: code under HIP graph capture of
+ * their own work around it, tight serving loops, harnesses that forbid
+ * allocation. The same evaluation as mdeos_eval_batch (lift + full schedule +
+ * restrict; the same results, bit for bit), without allocating anything: no
+ * hipMalloc / hipHostMalloc / hipFree, no HIP graphs, no C++ heap. Every
+ * device buffer the kernels use beyond specs and out lives in a static
+ * workspace of MDEOS_NOALLOC_SCRATCH_MIB MiB per GPU (held by each GPU the
+ * library runs on until the process ends); host staging is static too.
+ * Limits (MDEOS_INVALID_ARG beyond them, with mdeos_last_error saying which):
+ * n <= MDEOS_NOALLOC_MAX_CELLS; at most 16 groups of (atom count, image
+ * method); cell records, the atom state (72 B per atom), work lists and
+ * device-memory neighbour lists of at least one workgroup per group must fit
+ * the workspace (fewer workgroups are launched when the lists of more would
+ * not). No autotuning (the static launch-shape model) and no capacity retry:
+ * a cell that outgrows its planned capacities reports MDEOS_CELL_OVERFLOW.
+ * Uses ctx's device, stream, potential, precision and skins. specs[n] and
+ * out[n] are host arrays; blocks until out is written. Calls on one GPU share
+ * its workspace, which keeps the last call's contents: calls that overlap on
+ * one GPU would race, so this library serializes the calls of a process and
+ * returns only after their device work has ended. */
+#define MDEOS_NOALLOC_SCRATCH_MIB 64
+#define MDEOS_NOALLOC_MAX_CELLS 4096
+mdeos_status mdeos_eval_batch_noalloc(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs,
+                                      const mdeos_schedule* sched, mdeos_result* out, void* stream);
+
 mdeos_status mdeos_release(mdeos_ctx* ctx, int n, const mdeos_handle* h);
 
 /* Device time (ms, from HIP events on the launch stream) of the last

@@ -23,6 +23,9 @@ using namespace mdeos;
 static thread_local std::string g_last_error;
 
 static void set_error(const std::string& s) { g_last_error = s; }
+namespace mdeos {
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace mdeos
 
 const char* mdeos_last_error(void) { return g_last_error.c_str(); }
 
@@ -74,7 +77,7 @@ static int pick_ext(int need) {
 // a + b + c even, at coordinate l (a / 2 + 1/4).
 static int lattice_ghosts(int n_c, double l, double L, double rl) {
   const int m = 2 * n_c;
-  std::vector<int> img(m);
+  int img[2 * MDEOS_MAX_NC];  // n_c <= MDEOS_MAX_NC (validated); no allocation, the no-alloc path plans too
   for (int a = 0; a < m; ++a) {
     const double x = l * (0.5 * a + 0.25);
     img[a] = 1 + (x < rl ? 1 : 0) + (x >= L - rl ? 1 : 0);
@@ -326,6 +329,10 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   HCHECK(hipEventCreate(&ev_t1));
   if (init_kernel_attributes() != hipSuccess) {
     set_error("hipFuncSetAttribute failed");
+    return MDEOS_DEVICE_ERROR;
+  }
+  if (noalloc_init(device) != hipSuccess) {
+    set_error("hipGetSymbolAddress of the no-alloc workspace failed");
     return MDEOS_DEVICE_ERROR;
   }
   load_tune_cache();
@@ -1229,6 +1236,16 @@ extern "C" mdeos_status mdeos_eval_batch(mdeos_ctx* ctx, int n, const mdeos_cell
   if (n == 0) return MDEOS_OK;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   return c->eval(n, specs, sched, out, c->pick(stream), false);
+}
+
+extern "C" mdeos_status mdeos_eval_batch_noalloc(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs,
+                                                 const mdeos_schedule* sched, mdeos_result* out, void* stream) {
+  CTX_GUARD(C_(ctx));
+  Ctx* c = C_(ctx);
+  if (n < 0 || (n > 0 && (!specs || !sched || !out))) return MDEOS_INVALID_ARG;
+  if (n == 0) return MDEOS_OK;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  return c->eval_noalloc(n, specs, sched, out, c->pick(stream));
 }
 
 extern "C" mdeos_status mdeos_eval_plain(mdeos_ctx* ctx, int n, const mdeos_cell_spec* specs,

@@ -25,6 +25,8 @@ constexpr int kMaxBuckets = 64;
 
 double box_length(int n_c, double rho);
 int ring_for(int gmax);
+void set_last_error(const char* msg);   // message of mdeos_last_error (this thread)
+hipError_t noalloc_init(int device);    // the no-alloc workspace's address on `device` (current)
 
 struct CellPlan {
   int N = 0;
@@ -222,6 +224,8 @@ struct Ctx {
   mdeos_status fetch_results(int n, mdeos_result* out, hipStream_t s);
   mdeos_status eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched, mdeos_result* out,
                     hipStream_t s, bool plain);
+  mdeos_status eval_noalloc(int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched, mdeos_result* out,
+                            hipStream_t s);
 
   // autotuner
   void load_tune_cache();

@@ -76,6 +76,7 @@ EXPORTED = [
     "mdeos_strerror", "mdeos_last_error", "mdeos_version", "mdeos_validate", "mdeos_plan", "mdeos_cell_bytes",
     "mdeos_device_count", "mdeos_create", "mdeos_destroy", "mdeos_lift", "mdeos_lift_from_state",
     "mdeos_warm_start", "mdeos_advance", "mdeos_restrict", "mdeos_eval_batch", "mdeos_eval_plain",
+    "mdeos_eval_batch_noalloc",
     "mdeos_release", "mdeos_last_advance_time", "mdeos_state_export", "mdeos_debug_forces", "mdeos_debug_trajectory", "mdeos_serve_start",
     "mdeos_serve_submit", "mdeos_serve_poll", "mdeos_serve_now", "mdeos_serve_stats_get", "mdeos_serve_stop",
 ]
@@ -145,6 +146,7 @@ def lib() -> C.CDLL:
     L.mdeos_restrict.argtypes = [vp, C.c_int, P(C.c_longlong), P(Result), vp]
     L.mdeos_eval_batch.argtypes = [vp, C.c_int, P(CellSpec), P(Schedule), P(Result), vp]
     L.mdeos_eval_plain.argtypes = [vp, C.c_int, P(CellSpec), P(Schedule), P(Result), vp]
+    L.mdeos_eval_batch_noalloc.argtypes = [vp, C.c_int, P(CellSpec), P(Schedule), P(Result), vp]
     L.mdeos_release.argtypes = [vp, C.c_int, P(C.c_longlong)]
     L.mdeos_last_advance_time.argtypes = [vp, dp, P(C.c_int)]
     L.mdeos_state_export.argtypes = [vp, C.c_longlong, dp, dp, P(C.c_int)]
@@ -321,6 +323,14 @@ def mdeos_eval_batch(ctx, specs, sched: Schedule, stream=None) -> np.ndarray:
     specs = _spec_array(specs)
     out = (Result * len(specs))()
     _check(lib().mdeos_eval_batch(ctx, len(specs), specs, C.byref(sched), out, _stream(stream)), "mdeos_eval_batch")
+    return results_to_numpy(out)
+
+
+def mdeos_eval_batch_noalloc(ctx, specs, sched: Schedule, stream=None) -> np.ndarray:
+    specs = _spec_array(specs)
+    out = (Result * len(specs))()
+    _check(lib().mdeos_eval_batch_noalloc(ctx, len(specs), specs, C.byref(sched), out, _stream(stream)),
+           "mdeos_eval_batch_noalloc")
     return results_to_numpy(out)
 
 

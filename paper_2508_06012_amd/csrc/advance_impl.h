@@ -168,6 +168,11 @@ DEVI double wrap1(double x, double L) {
 // MI (minimum image): only the real atoms are held in LDS, binning cells
 // tile [0, L) periodically and every pair takes its nearest periodic image
 // (boxes with L >= 3 rl whose ghost-extended box would not fit in LDS).
+// Their LDS positions are 32-bit fixed-point fractions of the box edge
+// (unit L / 2^32, about 3e-9 sigma for the largest boxes): the wrapped
+// integer difference of two coordinates, read as signed, is the nearest-image
+// difference, so a pair costs an integer subtract and a conversion per axis
+// instead of an FP64 image correction, and a slot takes 12 bytes.
 // What the pair loop sums per atom besides the force.
 enum { ACC_F = 0, ACC_FW = 1, ACC_FWU = 2, ACC_FWUS = 3 };
 
@@ -175,7 +180,7 @@ template <int BLOCK, int APT, int EXT, bool LLDS, bool MI, bool NVT, bool EAM>
 struct Box {
   static constexpr int NW = BLOCK / 64;
   static constexpr int SENT = EXT - 1;  // padding neighbour index
-  using PT = typename std::conditional<MI, double, float>::type;  // LDS position type
+  using PT = typename std::conditional<MI, uint32_t, float>::type;  // LDS position type
   static constexpr int PB = sizeof(PT);
   // inner lists (device-memory lists of the embedded-atom shapes only: its two
   // walks per step are where they pay; the LJTS shapes carry none of their registers)
@@ -213,6 +218,7 @@ struct Box {
   CellRec* c;
   int N, G, n_pad, list_cap, ncell, nce, R;
   float L, rl, rl2, rc2, inv_ce;
+  float sL;  // fixed-point unit of the minimum-image positions, L / 2^32
   float rlc2;  // (rl in cell edges)^2, widened by a relative 1e-4 so clipping stays conservative
   float rin2, pthr;  // inner-list radius^2 (rc + prune_skin)^2; prune trigger (displacement^2)
   bool prune_cell;   // this cell keeps inner lists
@@ -245,9 +251,7 @@ struct Box {
   // build positions in FP32
   double x[APT], y[APT], z[APT], vx[APT], vy[APT], vz[APT];
   float fx[APT], fy[APT], fz[APT], bx[APT], by[APT], bz[APT];
-  double wi[APT], ui[APT];
-  float sv[6][APT];  // per-atom pair virial tensor of a sampled step (xx, yy, zz, xy, xz, yz)
-  int gofs[APT], gmask[APT], nblk[APT], cnt_in[APT];
+  int gofs[APT], gmask[APT], nblk[APT];
   int sslot[APT];  // slot of each owned atom (SORTED)
   int fnb[APT];                      // blocks of the list the force walks use (wave-uniform)
   float prx[APT], pry[APT], prz[APT];  // positions at the last prune
@@ -255,7 +259,7 @@ struct Box {
   int esteps;      // sampled (energy) steps in this launch
 
   DEVI Box(const AdvanceParams& pp, unsigned char* l) : p(pp), lds(l) {
-    lay = lds_layout(EXT, p.caps, LLDS, MI);
+    lay = lds_layout(EXT, p.caps, LLDS);
     px = (PT*)(lds + lay.pos);
     list = LLDS ? (uint16_t*)(lds + lay.list)
                 : p.gl_list + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
@@ -283,6 +287,30 @@ struct Box {
   DEVI PT& PX(int j) { return px[j]; }
   DEVI PT& PY(int j) { return px[EXT + j]; }
   DEVI PT& PZ(int j) { return px[2 * EXT + j]; }
+  // LDS form of a coordinate: FP32, or (MI) the fixed-point fraction of L of
+  // the wrapped coordinate, floor(2^32 frac(v / L)) (clamped below 2^32)
+  DEVI PT to_pt(double v) const {
+    if constexpr (MI) {
+      const double u = v * invLw;
+      return (uint32_t)fmin((u - floor(u)) * 4294967296.0, 4294967295.0);
+    } else {
+      return (float)v;
+    }
+  }
+  // a_i - a_j of two LDS coordinates as FP32 (MI: the nearest image)
+  DEVI float pdiff(PT a, PT b) const {
+    if constexpr (MI)
+      return (float)(int32_t)(a - b) * sL;
+    else
+      return a - b;
+  }
+  // FP32 coordinate of an LDS position (MI: in [0, L))
+  DEVI float pcoord(PT v) const {
+    if constexpr (MI)
+      return (float)v * sL;
+    else
+      return v;
+  }
 
   DEVI void load_cell(int cidx) {
     c = p.cells + cidx;
@@ -314,6 +342,7 @@ struct Box {
       pthr = 0.98f * 0.25f * ps * ps;
     }
     invLw = 1.0 / c->Lw;
+    sL = (float)(c->Lw * 0x1p-32);
     V = c->V;
     Ndof = 3.0 * N - 3.0;
     double irc2 = 1.0 / ((double)c->rc * (double)c->rc);
@@ -405,6 +434,17 @@ struct Box {
         dst[3 * g + 1] = sb;
         dst[3 * g + 2] = sc;
       }
+    }
+  }
+
+  // Per-group FP64 sums of one per-atom value into dst[3 g] (the K slot of a
+  // ring entry); each wave writes its own groups.
+  DEVI void group_sums1(const double (&a)[APT], double* dst) {
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      const double sa = wave_sum(a[k]);
+      const int g = k * NW + wv;
+      if (lane == 0 && g < p.caps.gmax) dst[3 * g] = sa;
     }
   }
 
@@ -555,12 +595,10 @@ struct Box {
     return u >= 1.0f ? min((int)fminf(u, (float)nce), nce - 1) : 0;
   }
   DEVI int wrapc(int q) const { return q < 0 ? q + nce : (q >= nce ? q - nce : q); }
-  // nearest periodic image of a coordinate difference (FP64 positions)
-  DEVI double mimg(double d) const { return fma(-Lw, rint(d * invLw), d); }
   DEVI int cell_xyz(float X, float Y, float Z) const {
     return (cell_coord(Z) * nce + cell_coord(Y)) * nce + cell_coord(X);
   }
-  DEVI int cell_of(int e) { return cell_xyz((float)PX(e), (float)PY(e), (float)PZ(e)); }
+  DEVI int cell_of(int e) { return cell_xyz(pcoord(PX(e)), pcoord(PY(e)), pcoord(PZ(e))); }
 
   // Builds ghosts, the binning and every atom's neighbour list from the
   // build positions (bx, by, bz). Returns false on a capacity overflow.
@@ -572,9 +610,9 @@ struct Box {
       gmask[k] = 0;
       if (a < N) {
         if (!SORTED) {
-          PX(a) = bx[k];
-          PY(a) = by[k];
-          PZ(a) = bz[k];
+          PX(a) = to_pt(bx[k]);
+          PY(a) = to_pt(by[k]);
+          PZ(a) = to_pt(bz[k]);
         }
         if (!MI) {
           gmask[k] = ghost_mask(bx[k], by[k], bz[k]);
@@ -711,6 +749,7 @@ struct Box {
       // self test drops. Pushed values are position offsets: slots when
       // SORTED, extended indices otherwise.
       const float bxi = bx[k], byi = by[k], bzi = bz[k];
+      const PT bpx = to_pt(bxi), bpy = to_pt(byi), bpz = to_pt(bzi);
       const int self = SORTED ? sslot[k] : a;
       auto scan = [&](int lo, int hi) __attribute__((always_inline)) {
         for (int q = lo; q < hi; q += 4) {
@@ -727,16 +766,7 @@ struct Box {
           float d2[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            float ddx, ddy, ddz;
-            if (MI) {
-              ddx = (float)mimg((double)bxi - (double)PX(e4[u]));
-              ddy = (float)mimg((double)byi - (double)PY(e4[u]));
-              ddz = (float)mimg((double)bzi - (double)PZ(e4[u]));
-            } else {
-              ddx = bxi - PX(e4[u]);
-              ddy = byi - PY(e4[u]);
-              ddz = bzi - PZ(e4[u]);
-            }
+            const float ddx = pdiff(bpx, PX(e4[u])), ddy = pdiff(bpy, PY(e4[u])), ddz = pdiff(bpz, PZ(e4[u]));
             d2[u] = fmaf(ddx, ddx, fmaf(ddy, ddy, ddz * ddz));
           }
 #pragma unroll
@@ -840,9 +870,9 @@ struct Box {
       int a = t + k * BLOCK;
       if (a < N) {
         const int sl = SORTED ? sslot[k] : a;
-        PX(sl) = (PT)x[k];
-        PY(sl) = (PT)y[k];
-        PZ(sl) = (PT)z[k];
+        PX(sl) = to_pt(x[k]);
+        PY(sl) = to_pt(y[k]);
+        PZ(sl) = to_pt(z[k]);
         if (gmask[k]) {
           if (SORTED)
             write_images_sorted(x[k], y[k], z[k], gmask[k], gofs[k]);
@@ -868,6 +898,32 @@ struct Box {
     }
     if (t == 0) c->n_builds += 1;  // chunk-start reconstructions are not counted
     return build_lists();
+  }
+
+  // Per-group sums of one atom's walk, formed right after it so that no
+  // per-atom sum outlives the walk in registers: for owned atom k, the wave
+  // owning its group g adds the halved virial w and energy u (full lists see
+  // every pair twice) and the halved pair virial tensor s6 over its 64 lanes,
+  // and lane 0 writes them (0 where ACC does not ask for a value; atoms past
+  // N add 0). The in-range pair count goes to pairs_t on energy steps.
+  template <int ACC>
+  DEVI void walk_sums(int k, double w, double u, int cin, const float (&s6)[6], double* gdst, double* tdst) {
+    const bool v = valid(k);
+    const int g = k * NW + wv;
+    const double W = ACC >= ACC_FW ? wave_sum(v ? 0.5 * w : 0.0) : 0.0;
+    const double U = ACC >= ACC_FWU ? wave_sum(v ? 0.5 * u : 0.0) : 0.0;
+    if (ACC >= ACC_FWU) pairs_t += (double)(v ? cin : 0);
+    if (lane == 0 && g < p.caps.gmax) {
+      gdst[3 * g + 1] = W;
+      gdst[3 * g + 2] = U;
+    }
+    if (ACC == ACC_FWUS) {
+#pragma unroll
+      for (int c6 = 0; c6 < 6; ++c6) {
+        const double sc = wave_sum(v ? 0.5 * (double)s6[c6] : 0.0);
+        if (lane == 0 && g < p.caps.gmax) tdst[6 * g + c6] = sc;
+      }
+    }
   }
 
   // --- pair forces (LJTS, FP32) -------------------------------------------------
@@ -920,8 +976,7 @@ struct Box {
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       const int a = t + k * BLOCK;
-      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
-      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      const PT xi = to_pt(x[k]), yi = to_pt(y[k]), zi = to_pt(z[k]);
       int cnt = 0;
       auto block = [&](const uint4 ent) __attribute__((always_inline)) {
         const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
@@ -929,16 +984,7 @@ struct Box {
         for (int m = 0; m < 8; ++m) {
           const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
           const PT* q = reinterpret_cast<const PT*>(pb + off);
-          float dx, dy, dz;
-          if (MI) {
-            dx = (float)mimg(xi64 - q[0]);
-            dy = (float)mimg(yi64 - q[EXT]);
-            dz = (float)mimg(zi64 - q[2 * EXT]);
-          } else {
-            dx = xi - q[0];
-            dy = yi - q[EXT];
-            dz = zi - q[2 * EXT];
-          }
+          const float dx = pdiff(xi, q[0]), dy = pdiff(yi, q[EXT]), dz = pdiff(zi, q[2 * EXT]);
           const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
           if (MI ? (r2 < rin2 && r2 > 0.0f) : r2 < rin2) {
             // cnt never exceeds the entries of the outer row (< list_cap)
@@ -957,22 +1003,21 @@ struct Box {
         const uint32_t pp = (uint32_t)pad * 0x00010001u;
         for (int b = q >> 3; b < nb; ++b) reinterpret_cast<uint4*>(ilist)[b * n_pad + a] = make_uint4(pp, pp, pp, pp);
       }
-      prx[k] = xi;
-      pry[k] = yi;
-      prz[k] = zi;
+      prx[k] = (float)x[k];
+      pry[k] = (float)y[k];
+      prz[k] = (float)z[k];
     }
     inner = true;
     __syncthreads();
   }
 
   template <int ACC, bool KAHAN>
-  DEVI void forces_impl() {
+  DEVI void forces_impl(double* gdst, double* tdst) {
     const char* pb = reinterpret_cast<const char*>(px);
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       const int a = t + k * BLOCK;
-      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
-      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      const PT xi = to_pt(x[k]), yi = to_pt(y[k]), zi = to_pt(z[k]);
       float ax = 0.f, ay = 0.f, az = 0.f;
       double wd = 0.0, ud = 0.0;                  // FP64 sums
       float ws = 0.f, wc = 0.f, us = 0.f, uc = 0.f;  // Kahan sums and compensations
@@ -986,17 +1031,7 @@ struct Box {
         for (int m = 0; m < 8; ++m) {
           const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
           const PT* q = reinterpret_cast<const PT*>(pb + off);
-          float dx, dy, dz;
-          if (MI) {
-            // image-corrected difference in FP64, then FP32 pair math
-            dx = (float)mimg(xi64 - q[0]);
-            dy = (float)mimg(yi64 - q[EXT]);
-            dz = (float)mimg(zi64 - q[2 * EXT]);
-          } else {
-            dx = xi - q[0];
-            dy = yi - q[EXT];
-            dz = zi - q[2 * EXT];
-          }
+          const float dx = pdiff(xi, q[0]), dy = pdiff(yi, q[EXT]), dz = pdiff(zi, q[2 * EXT]);
           const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
           const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
           const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
@@ -1050,13 +1085,7 @@ struct Box {
         wd = (double)ws - (double)wc;
         ud = (double)us - (double)uc;
       }
-      wi[k] = ACC >= ACC_FW ? wd : 0.0;
-      ui[k] = ACC >= ACC_FWU ? fma(-(double)cin, u_shift, 4.0 * ud) : 0.0;
-      cnt_in[k] = (ACC >= ACC_FWU && a < N) ? cin : 0;
-      if (ACC == ACC_FWUS) {
-        sv[0][k] = sxx; sv[1][k] = syy; sv[2][k] = szz;
-        sv[3][k] = sxy; sv[4][k] = sxz; sv[5][k] = syz;
-      }
+      walk_sums<ACC>(k, wd, fma(-(double)cin, u_shift, 4.0 * ud), cin, {sxx, syy, szz, sxy, sxz, syz}, gdst, tdst);
     }
   }
 
@@ -1076,8 +1105,7 @@ struct Box {
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       const int a = t + k * BLOCK;
-      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
-      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      const PT xi = to_pt(x[k]), yi = to_pt(y[k]), zi = to_pt(z[k]);
       float rs = 0.f;
       auto block = [&](const uint4 ent) __attribute__((always_inline)) {
         const uint32_t wd4[4] = {ent.x, ent.y, ent.z, ent.w};
@@ -1085,16 +1113,7 @@ struct Box {
         for (int m = 0; m < 8; ++m) {
           const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
           const PT* q = reinterpret_cast<const PT*>(pb + off);
-          float dx, dy, dz;
-          if (MI) {
-            dx = (float)mimg(xi64 - q[0]);
-            dy = (float)mimg(yi64 - q[EXT]);
-            dz = (float)mimg(zi64 - q[2 * EXT]);
-          } else {
-            dx = xi - q[0];
-            dy = yi - q[EXT];
-            dz = zi - q[2 * EXT];
-          }
+          const float dx = pdiff(xi, q[0]), dy = pdiff(yi, q[EXT]), dz = pdiff(zi, q[2 * EXT]);
           const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
           const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
           const float ir = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
@@ -1117,7 +1136,7 @@ struct Box {
   }
 
   template <int ACC, bool KAHAN>
-  DEVI void eam_forces_impl() {
+  DEVI void eam_forces_impl(double* gdst, double* tdst) {
     float fpi[APT];
     double emb[APT];
     eam_density(fpi, emb);
@@ -1127,8 +1146,7 @@ struct Box {
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
       const int a = t + k * BLOCK;
-      const float xi = (float)x[k], yi = (float)y[k], zi = (float)z[k];
-      const double xi64 = x[k], yi64 = y[k], zi64 = z[k];
+      const PT xi = to_pt(x[k]), yi = to_pt(y[k]), zi = to_pt(z[k]);
       const float fpk = fpi[k];
       float ax = 0.f, ay = 0.f, az = 0.f;
       double wd = 0.0, ud = 0.0;
@@ -1141,18 +1159,9 @@ struct Box {
         for (int m = 0; m < 8; ++m) {
           const uint32_t off = (m & 1) ? (wd4[m >> 1] >> 16) : (wd4[m >> 1] & 0xffffu);
           const PT* q = reinterpret_cast<const PT*>(pb + off);
-          // F' of neighbour j: float slot j (the offset is j * sizeof(PT))
-          const float fpj = *reinterpret_cast<const float*>(fb + (MI ? (off >> 1) : off));
-          float dx, dy, dz;
-          if (MI) {
-            dx = (float)mimg(xi64 - q[0]);
-            dy = (float)mimg(yi64 - q[EXT]);
-            dz = (float)mimg(zi64 - q[2 * EXT]);
-          } else {
-            dx = xi - q[0];
-            dy = yi - q[EXT];
-            dz = zi - q[2 * EXT];
-          }
+          // F' of neighbour j: float slot j (the offset is 4 j)
+          const float fpj = *reinterpret_cast<const float*>(fb + off);
+          const float dx = pdiff(xi, q[0]), dy = pdiff(yi, q[EXT]), dz = pdiff(zi, q[2 * EXT]);
           const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
           const bool in = MI ? (r2 < rc2 && r2 > 0.0f) : r2 < rc2;
           const float ir = in ? __builtin_amdgcn_rsqf(r2) : 0.0f;
@@ -1210,29 +1219,26 @@ struct Box {
         wd = (double)ws - (double)wc;
         ud = (double)us - (double)uc;
       }
-      wi[k] = ACC >= ACC_FW ? wd : 0.0;
-      // halved with the pair terms: 1/2 sum_j V_s + F(rhobar_i)
-      ui[k] = ACC >= ACC_FWU ? ud + emb[k] : 0.0;
-      cnt_in[k] = (ACC >= ACC_FWU && a < N) ? cin : 0;
-      if (ACC == ACC_FWUS) {
-        sv[0][k] = sxx; sv[1][k] = syy; sv[2][k] = szz;
-        sv[3][k] = sxy; sv[4][k] = sxz; sv[5][k] = syz;
-      }
+      // sum_j V_s + 2 F(rhobar_i), halved with the pair terms below
+      walk_sums<ACC>(k, wd, ud + emb[k], cin, {sxx, syy, szz, sxy, sxz, syz}, gdst, tdst);
     }
   }
 
+  // Forces of every owned atom into (fx, fy, fz), and per 64-atom group the
+  // halved sums ACC asks for: W / 2 and E_pot / 2 into gdst[3 g + 1] and
+  // gdst[3 g + 2], the pair virial tensor / 2 into tdst[6 g + c].
   template <int ACC>
-  DEVI void forces() {
+  DEVI void forces(double* gdst, double* tdst = nullptr) {
     if (EAM) {
       if (kahan)
-        eam_forces_impl<ACC, true>();
+        eam_forces_impl<ACC, true>(gdst, tdst);
       else
-        eam_forces_impl<ACC, false>();
+        eam_forces_impl<ACC, false>(gdst, tdst);
     } else {
       if (kahan)
-        forces_impl<ACC, true>();
+        forces_impl<ACC, true>(gdst, tdst);
       else
-        forces_impl<ACC, false>();
+        forces_impl<ACC, false>(gdst, tdst);
     }
   }
 
@@ -1442,19 +1448,21 @@ struct Box {
     if (!rebuild()) return false;
     refresh_positions();
     __syncthreads();
-    forces<ACC_FWU>();
-    double ua[APT], wa[APT], za[APT];
-#pragma unroll
-    for (int k = 0; k < APT; ++k) {
-      bool v = valid(k);
-      ua[k] = v ? ui[k] : 0.0;
-      wa[k] = v ? wi[k] : 0.0;
-      za[k] = 0.0;
+    forces<ACC_FWU>(red);
+    __syncthreads();
+    if (t == 0) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int g = 0; g < G; ++g) {
+        s1 += red[3 * g + 1];
+        s2 += red[3 * g + 2];
+      }
+      ctl->scal[1] = s1;
+      ctl->scal[2] = s2;
     }
-    double zz;
-    reduce_now(ua, wa, za, U, W, zz);
-    U *= 0.5;  // full lists count every pair twice
-    W *= 0.5;
+    __syncthreads();
+    W = ctl->scal[1];
+    U = ctl->scal[2];
+    __syncthreads();
     return true;
   }
 
@@ -1730,28 +1738,32 @@ struct Box {
       const bool energy = is_energy_step(k);
       // steps where the stress tensor of Eq. stress is sampled (as <E_pot>)
       const bool sample = energy && k > n_steps - n_avg && (k % energy_every == 0 || k == n_steps);
+      // this step's ring slot: the walks write W and E_pot per group, the
+      // kinetic sums below K
+      double* slot = ring + (size_t)(k % RING) * 3 * p.caps.gmax;
       if (sample) {
-        forces<ACC_FWUS>();
-#pragma unroll
-        for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
+        forces<ACC_FWUS>(slot, red);
         ++esteps;
-        double vt[6][APT];  // pair virial tensor, halved: full lists see each pair twice
+        // pair virial tensor (halved per group by the walks), groups in order
+        __syncthreads();
+        if (t == 0) {
 #pragma unroll
-        for (int q = 0; q < APT; ++q)
-#pragma unroll
-          for (int c6 = 0; c6 < 6; ++c6) vt[c6][q] = valid(q) ? 0.5 * (double)sv[c6][q] : 0.0;
-        tensor_add(vt, ctl->sigV);
+          for (int c6 = 0; c6 < 6; ++c6) {
+            double sc = 0.0;
+            for (int g = 0; g < G; ++g) sc += red[6 * g + c6];
+            ctl->sigV[c6] += sc;
+          }
+        }
+        __syncthreads();
       } else if (energy) {
-        forces<ACC_FWU>();
-#pragma unroll
-        for (int q = 0; q < APT; ++q) pairs_t += (double)cnt_in[q];
+        forces<ACC_FWU>(slot);
         ++esteps;
       } else if (k > n_steps - n_avg || debug_energy) {
-        forces<ACC_FW>();  // the virial enters P only inside the averaging window
+        forces<ACC_FW>(slot);  // the virial enters P only inside the averaging window
       } else {
-        forces<ACC_F>();
+        forces<ACC_F>(slot);
       }
-      double ka[APT], wa[APT], ua[APT];
+      double ka[APT];
 #pragma unroll
       for (int q = 0; q < APT; ++q) {
         if (nvt) {
@@ -1768,12 +1780,9 @@ struct Box {
           vy[q] = fma(hdt, (double)fy[q], vy[q]);
           vz[q] = fma(hdt, (double)fz[q], vz[q]);
         }
-        const bool v = valid(q);
-        ka[q] = v ? 0.5 * fma(vx[q], vx[q], fma(vy[q], vy[q], vz[q] * vz[q])) : 0.0;
-        wa[q] = v ? 0.5 * wi[q] : 0.0;
-        ua[q] = (v && energy) ? 0.5 * ui[q] : 0.0;
+        ka[q] = valid(q) ? 0.5 * fma(vx[q], vx[q], fma(vy[q], vy[q], vz[q] * vz[q])) : 0.0;
       }
-      group_sums(ka, wa, ua, ring + (size_t)(k % RING) * 3 * p.caps.gmax);
+      group_sums1(ka, slot);
       if (sample) {
         double kt[6][APT];  // kinetic tensor m v_a v_b
 #pragma unroll
@@ -1876,9 +1885,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
   extern __shared__ __align__(16) unsigned char lds[];
   Box<BLOCK, APT, EXT, LLDS, MI, NVT, EAM> box(p, lds);
   if (threadIdx.x == 0) {
-    box.PX(EXT - 1) = kSentinelPos;
-    box.PY(EXT - 1) = kSentinelPos;
-    box.PZ(EXT - 1) = kSentinelPos;
+    // the padding neighbour (minimum-image lists pad with the atom itself;
+    // there only threads past the last atom name this slot)
+    box.PX(EXT - 1) = MI ? 0 : kSentinelPos;
+    box.PY(EXT - 1) = MI ? 0 : kSentinelPos;
+    box.PZ(EXT - 1) = MI ? 0 : kSentinelPos;
   }
   const int n_work = p.meta[0];
   const int* work = p.work_base + p.meta[1];

@@ -168,7 +168,7 @@ mdeos_status finish_plan(CellPlan& out) {
   c.ncell_cap = out.ncell;
   c.gmax = c.n_pad / 64;
   c.ring = ring_for(c.gmax);
-  LdsLayout with = lds_layout(out.ext, c, true, out.minimg), without = lds_layout(out.ext, c, false, out.minimg);
+  LdsLayout with = lds_layout(out.ext, c, true), without = lds_layout(out.ext, c, false);
   out.list_in_lds = with.total <= kLdsMax ? 1 : 0;
   out.lds_bytes = out.list_in_lds ? with.total : without.total;
   if (out.lds_bytes > kLdsMax) return MDEOS_INVALID_ARG;
@@ -630,7 +630,7 @@ int Ctx::rank_variants(const CellPlan& p, std::vector<Variant>& out) const {
   std::vector<std::pair<int, int>> scored;
   for (int i = 0; i < variant_count(); ++i) {
     const Variant v = variant_at(i);
-    const int lds = lds_layout(v.ext, c, v.list_lds, v.mi).total;
+    const int lds = lds_layout(v.ext, c, v.list_lds).total;
     if (v.mi != p.minimg || v.nvt != p.nvt || v.eam != (potential == MDEOS_POT_EAM ? 1 : 0) ||
         v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax)
       continue;
@@ -695,7 +695,7 @@ mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) 
     std::vector<Bucket> one{b};
     auto use = [&](const Variant& v) {
       one[0].v = v;
-      one[0].lds = lds_layout(v.ext, one[0].caps, v.list_lds, v.mi).total;
+      one[0].lds = lds_layout(v.ext, one[0].caps, v.list_lds).total;
       one[0].grid = std::max(1, std::min<int>((int)b.cells.size(), std::max(1, occupancy(v, one[0].lds)) * n_cu));
     };
     use(b.v);
@@ -717,7 +717,7 @@ mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) 
     tuned[key] = cand[w];
     changed = true;
     b.v = cand[w];
-    b.lds = lds_layout(b.v.ext, b.caps, b.v.list_lds, b.v.mi).total;
+    b.lds = lds_layout(b.v.ext, b.caps, b.v.list_lds).total;
     b.grid = std::max(1, std::min<int>((int)b.cells.size(), std::max(1, occupancy(b.v, b.lds)) * n_cu));
     ++tune_runs;
   }
@@ -795,7 +795,7 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
     b.v = v;
     b.plan = merged;
     b.caps = caps_of(merged);
-    b.lds = lds_layout(v.ext, b.caps, v.list_lds, v.mi).total;
+    b.lds = lds_layout(v.ext, b.caps, v.list_lds).total;
     b.cells = cs;
     // longest first
     std::stable_sort(b.cells.begin(), b.cells.end(), [&](int a, int c) {
@@ -868,10 +868,11 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
     std::vector<int> order(buckets.size());
     for (size_t i = 0; i < buckets.size(); ++i) {
       order[i] = (int)i;
-      // minimum-image pairs cost about 1.6 times more (FP64 image differences)
+      // a minimum-image pair costs about 1.3 times a ghost-image one (the
+      // fixed-point image difference adds a conversion and a multiply per axis)
       for (int c : buckets[i].cells)
         cost[i] += (double)cell_plan[c].N * cell_plan[c].list_cap * std::max(1, h_cells[c].n_steps - h_cells[c].step) *
-                   (cell_plan[c].minimg ? 1.6 : 1.0);
+                   (cell_plan[c].minimg ? 1.3 : 1.0);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     for (int i : order) {

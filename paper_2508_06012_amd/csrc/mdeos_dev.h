@@ -116,11 +116,10 @@ struct AdvanceParams {
 
 // LDS layout of one box. EXT is the stride of each position array (compile
 // time), so the three coordinates of neighbour j sit at byte offsets
-// s j, s (j + EXT) and s (j + 2 EXT) (s = 4 for float, 8 for the FP64
-// positions of the minimum-image variant) and one VGPR address serves all
-// three loads.
+// 4 j, 4 (j + EXT) and 4 (j + 2 EXT) and one VGPR address serves all three
+// loads.
 struct LdsLayout {
-  int pos;        // float[3][EXT] (double[3][EXT] for minimum image)
+  int pos;        // float[3][EXT] (uint32[3][EXT] fixed point for minimum image)
   int list;       // uint16[list_cap/8][n_pad][8] (when the list lives in LDS)
   int tmp;        // uint16[EXT]   (the ghost-count scan uses tmp..sorted as int[N]; outside the
                   //                list build the embedded-atom forces keep F'(rhobar) there as float[EXT])
@@ -128,17 +127,17 @@ struct LdsLayout {
   int cstart;     // int[ncell_cap + 1]
   int cfill;      // int[ncell_cap]
   int ring;       // double[ring][gmax][3]
-  int red;        // double[64][4]
+  int red;        // double[gmax][6] (per-group sums of up to six values)
   int ctl;        // control block (int/float/double scalars)
   int total;
 };
 
 __host__ __device__ inline int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
-__host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool list_in_lds, bool mi = false) {
+__host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool list_in_lds) {
   LdsLayout l;
   int o = 0;
-  l.pos = o; o += (mi ? 24 : 12) * ext;
+  l.pos = o; o += 12 * ext;
   l.list = o; o += list_in_lds ? 2 * c.list_cap * c.n_pad : 0;
   o = align_up(o, 16);
   l.tmp = o; o += 2 * ext;
@@ -148,7 +147,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
   l.cfill = o; o += 4 * c.ncell_cap;
   o = align_up(o, 16);
   l.ring = o; o += 8 * 3 * c.gmax * c.ring;
-  l.red = o; o += 8 * 4 * 64;
+  l.red = o; o += 8 * 6 * c.gmax;
   l.ctl = o; o += 1024;
   l.total = align_up(o, 256);
   return l;

@@ -194,6 +194,10 @@ struct Box {
   // extended index, so the bits do not change. (The embedded-atom shapes keep
   // F'(rhobar) where the map would live; minimum-image boxes hold no images.)
   static constexpr bool SORTED = !MI && !EAM;
+  // Forces of the minimum-image shapes with four or more atoms per thread
+  // live in LDS (float[3][BLOCK * APT]), not in registers: those boxes leave
+  // LDS to spare, and their per-atom state otherwise outgrows the registers.
+  static constexpr bool FLDS = forces_in_lds(MI, APT);
 
   const AdvanceParams& p;
   LdsLayout lay;
@@ -208,6 +212,7 @@ struct Box {
   uint16_t* ilist;
   bool inner;
   uint16_t *tmp, *sorted;
+  float* frc;  // forces in LDS (FLDS)
   float* fpv;  // F'(rhobar) per position slot (embedded-atom forces; shares tmp/sorted, live outside list builds)
   int *cstart, *cfill, *scanbuf;
   double *ring, *red;
@@ -259,7 +264,7 @@ struct Box {
   int esteps;      // sampled (energy) steps in this launch
 
   DEVI Box(const AdvanceParams& pp, unsigned char* l) : p(pp), lds(l) {
-    lay = lds_layout(EXT, p.caps, LLDS);
+    lay = lds_layout(EXT, p.caps, LLDS, FLDS ? BLOCK * APT : 0);
     px = (PT*)(lds + lay.pos);
     list = LLDS ? (uint16_t*)(lds + lay.list)
                 : p.gl_list + (size_t)blockIdx.x * (size_t)p.caps.list_cap * (size_t)p.caps.n_pad;
@@ -273,6 +278,7 @@ struct Box {
     cfill = (int*)(lds + lay.cfill);
     scanbuf = (int*)(lds + lay.tmp);
     fpv = (float*)(lds + lay.tmp);
+    frc = (float*)(lds + lay.frc);
     ring = (double*)(lds + lay.ring);
     red = (double*)(lds + lay.red);
     ctl = (Ctl*)(lds + lay.ctl);
@@ -284,6 +290,19 @@ struct Box {
     kahan = p.kahan != 0;
   }
 
+  // force components of owned atom k
+  DEVI float& FX(int k) {
+    if constexpr (FLDS) return frc[t + k * BLOCK];
+    else return fx[k];
+  }
+  DEVI float& FY(int k) {
+    if constexpr (FLDS) return frc[BLOCK * APT + t + k * BLOCK];
+    else return fy[k];
+  }
+  DEVI float& FZ(int k) {
+    if constexpr (FLDS) return frc[2 * BLOCK * APT + t + k * BLOCK];
+    else return fz[k];
+  }
   DEVI PT& PX(int j) { return px[j]; }
   DEVI PT& PY(int j) { return px[EXT + j]; }
   DEVI PT& PZ(int j) { return px[2 * EXT + j]; }
@@ -1078,9 +1097,9 @@ struct Box {
         }
       };
       walk_list(force_list(), a, nb, block);
-      fx[k] = ax;
-      fy[k] = ay;
-      fz[k] = az;
+      FX(k) = ax;
+      FY(k) = ay;
+      FZ(k) = az;
       if (KAHAN) {
         wd = (double)ws - (double)wc;
         ud = (double)us - (double)uc;
@@ -1212,9 +1231,9 @@ struct Box {
         }
       };
       walk_list(force_list(), a, force_blocks(k), block);
-      fx[k] = ax;
-      fy[k] = ay;
-      fz[k] = az;
+      FX(k) = ax;
+      FY(k) = ay;
+      FZ(k) = az;
       if (KAHAN) {
         wd = (double)ws - (double)wc;
         ud = (double)us - (double)uc;
@@ -1339,11 +1358,11 @@ struct Box {
       if (a < N) {
         x[k] = p.a.x[off + a]; y[k] = p.a.y[off + a]; z[k] = p.a.z[off + a];
         vx[k] = p.a.vx[off + a]; vy[k] = p.a.vy[off + a]; vz[k] = p.a.vz[off + a];
-        fx[k] = p.a.fx[off + a]; fy[k] = p.a.fy[off + a]; fz[k] = p.a.fz[off + a];
+        FX(k) = p.a.fx[off + a]; FY(k) = p.a.fy[off + a]; FZ(k) = p.a.fz[off + a];
         bx[k] = p.a.bx[off + a]; by[k] = p.a.by[off + a]; bz[k] = p.a.bz[off + a];
       } else {
         x[k] = y[k] = z[k] = vx[k] = vy[k] = vz[k] = 0.0;
-        fx[k] = fy[k] = fz[k] = bx[k] = by[k] = bz[k] = 0.f;
+        FX(k) = FY(k) = FZ(k) = bx[k] = by[k] = bz[k] = 0.f;
       }
     }
   }
@@ -1355,7 +1374,7 @@ struct Box {
       if (a < N) {
         p.a.x[off + a] = x[k]; p.a.y[off + a] = y[k]; p.a.z[off + a] = z[k];
         p.a.vx[off + a] = vx[k]; p.a.vy[off + a] = vy[k]; p.a.vz[off + a] = vz[k];
-        p.a.fx[off + a] = fx[k]; p.a.fy[off + a] = fy[k]; p.a.fz[off + a] = fz[k];
+        p.a.fx[off + a] = FX(k); p.a.fy[off + a] = FY(k); p.a.fz[off + a] = FZ(k);
         p.a.bx[off + a] = bx[k]; p.a.by[off + a] = by[k]; p.a.bz[off + a] = bz[k];
       }
     }
@@ -1680,16 +1699,16 @@ struct Box {
             // GJF first half: u = sqrt(b) (v + dt f / 2 + beta / 2); x += sqrt(b) dt u
             double z0, z1, z2;
             noise3(seed, cell_id, t + q * BLOCK, k, query, z0, z1, z2);
-            vx[q] = gjf_sb * fma(hdt, (double)fx[q], fma(hsig, z0, vx[q]));
-            vy[q] = gjf_sb * fma(hdt, (double)fy[q], fma(hsig, z1, vy[q]));
-            vz[q] = gjf_sb * fma(hdt, (double)fz[q], fma(hsig, z2, vz[q]));
+            vx[q] = gjf_sb * fma(hdt, (double)FX(q), fma(hsig, z0, vx[q]));
+            vy[q] = gjf_sb * fma(hdt, (double)FY(q), fma(hsig, z1, vy[q]));
+            vz[q] = gjf_sb * fma(hdt, (double)FZ(q), fma(hsig, z2, vz[q]));
             x[q] = fma(gjf_sb * dt, vx[q], x[q]);
             y[q] = fma(gjf_sb * dt, vy[q], y[q]);
             z[q] = fma(gjf_sb * dt, vz[q], z[q]);
           } else {
-            vx[q] = fma(hdt, (double)fx[q], vx[q]);
-            vy[q] = fma(hdt, (double)fy[q], vy[q]);
-            vz[q] = fma(hdt, (double)fz[q], vz[q]);
+            vx[q] = fma(hdt, (double)FX(q), vx[q]);
+            vy[q] = fma(hdt, (double)FY(q), vy[q]);
+            vz[q] = fma(hdt, (double)FZ(q), vz[q]);
             x[q] = fma(dt, vx[q], x[q]);
             y[q] = fma(dt, vy[q], y[q]);
             z[q] = fma(dt, vz[q], z[q]);
@@ -1771,14 +1790,14 @@ struct Box {
           if (valid(q)) {
             double z0, z1, z2;
             noise3(seed, cell_id, t + q * BLOCK, k, query, z0, z1, z2);
-            vx[q] = fma(gjf_a_sb, vx[q], fma(hdt, (double)fx[q], hsig * z0));
-            vy[q] = fma(gjf_a_sb, vy[q], fma(hdt, (double)fy[q], hsig * z1));
-            vz[q] = fma(gjf_a_sb, vz[q], fma(hdt, (double)fz[q], hsig * z2));
+            vx[q] = fma(gjf_a_sb, vx[q], fma(hdt, (double)FX(q), hsig * z0));
+            vy[q] = fma(gjf_a_sb, vy[q], fma(hdt, (double)FY(q), hsig * z1));
+            vz[q] = fma(gjf_a_sb, vz[q], fma(hdt, (double)FZ(q), hsig * z2));
           }
         } else {
-          vx[q] = fma(hdt, (double)fx[q], vx[q]);
-          vy[q] = fma(hdt, (double)fy[q], vy[q]);
-          vz[q] = fma(hdt, (double)fz[q], vz[q]);
+          vx[q] = fma(hdt, (double)FX(q), vx[q]);
+          vy[q] = fma(hdt, (double)FY(q), vy[q]);
+          vz[q] = fma(hdt, (double)FZ(q), vz[q]);
         }
         ka[q] = valid(q) ? 0.5 * fma(vx[q], vx[q], fma(vy[q], vy[q], vz[q] * vz[q])) : 0.0;
       }

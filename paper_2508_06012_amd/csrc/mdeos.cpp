@@ -630,7 +630,7 @@ int Ctx::rank_variants(const CellPlan& p, std::vector<Variant>& out) const {
   std::vector<std::pair<int, int>> scored;
   for (int i = 0; i < variant_count(); ++i) {
     const Variant v = variant_at(i);
-    const int lds = lds_layout(v.ext, c, v.list_lds).total;
+    const int lds = lds_layout(v.ext, c, v.list_lds, frc_slots(v)).total;
     if (v.mi != p.minimg || v.nvt != p.nvt || v.eam != (potential == MDEOS_POT_EAM ? 1 : 0) ||
         v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax)
       continue;
@@ -695,7 +695,7 @@ mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) 
     std::vector<Bucket> one{b};
     auto use = [&](const Variant& v) {
       one[0].v = v;
-      one[0].lds = lds_layout(v.ext, one[0].caps, v.list_lds).total;
+      one[0].lds = lds_layout(v.ext, one[0].caps, v.list_lds, frc_slots(v)).total;
       one[0].grid = std::max(1, std::min<int>((int)b.cells.size(), std::max(1, occupancy(v, one[0].lds)) * n_cu));
     };
     use(b.v);
@@ -717,7 +717,7 @@ mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) 
     tuned[key] = cand[w];
     changed = true;
     b.v = cand[w];
-    b.lds = lds_layout(b.v.ext, b.caps, b.v.list_lds).total;
+    b.lds = lds_layout(b.v.ext, b.caps, b.v.list_lds, frc_slots(b.v)).total;
     b.grid = std::max(1, std::min<int>((int)b.cells.size(), std::max(1, occupancy(b.v, b.lds)) * n_cu));
     ++tune_runs;
   }
@@ -795,7 +795,7 @@ void Ctx::make_buckets(const std::vector<int>& cells, std::vector<Bucket>& out, 
     b.v = v;
     b.plan = merged;
     b.caps = caps_of(merged);
-    b.lds = lds_layout(v.ext, b.caps, v.list_lds).total;
+    b.lds = lds_layout(v.ext, b.caps, v.list_lds, frc_slots(v)).total;
     b.cells = cs;
     // longest first
     std::stable_sort(b.cells.begin(), b.cells.end(), [&](int a, int c) {
@@ -861,18 +861,26 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
     const int na = std::min<int>(kAux, (int)buckets.size());
     for (int i = 0; i < na; ++i)
       if ((e = hipStreamWaitEvent(aux[i], ev_fork, 0)) != hipSuccess) return e;
-    // Longest processing time first: buckets in decreasing estimated cost,
-    // each on the stream with the least cost so far, so the largest start at
-    // once and the small ones fill in around them.
+    // Longest processing time first: buckets in decreasing estimated
+    // duration, each on the stream with the least duration so far, so the
+    // longest start at once and the short ones fill in around them. A
+    // bucket lasts at least as long as its longest cell (one workgroup
+    // advances a cell), and about its total cost over its workgroups when
+    // it has many cells; a few large cells must therefore start early.
     std::vector<double> cost(buckets.size(), 0.0), load(na, 0.0);
     std::vector<int> order(buckets.size());
     for (size_t i = 0; i < buckets.size(); ++i) {
       order[i] = (int)i;
+      double total = 0.0, longest = 0.0;
       // a minimum-image pair costs about 1.3 times a ghost-image one (the
       // fixed-point image difference adds a conversion and a multiply per axis)
-      for (int c : buckets[i].cells)
-        cost[i] += (double)cell_plan[c].N * cell_plan[c].list_cap * std::max(1, h_cells[c].n_steps - h_cells[c].step) *
-                   (cell_plan[c].minimg ? 1.3 : 1.0);
+      for (int c : buckets[i].cells) {
+        const double one = (double)cell_plan[c].N * cell_plan[c].list_cap *
+                           std::max(1, h_cells[c].n_steps - h_cells[c].step) * (cell_plan[c].minimg ? 1.3 : 1.0);
+        total += one;
+        longest = std::max(longest, one);
+      }
+      cost[i] = std::max(total / std::max(1, buckets[i].grid), longest);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     for (int i : order) {

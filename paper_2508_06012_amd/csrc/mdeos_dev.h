@@ -129,12 +129,13 @@ struct LdsLayout {
   int ring;       // double[ring][gmax][3]
   int red;        // double[gmax][6] (per-group sums of up to six values)
   int ctl;        // control block (int/float/double scalars)
+  int frc;        // float[3][frc_slots]: forces of the shapes that keep them in LDS
   int total;
 };
 
 __host__ __device__ inline int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
-__host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool list_in_lds) {
+__host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool list_in_lds, int frc_slots = 0) {
   LdsLayout l;
   int o = 0;
   l.pos = o; o += 12 * ext;
@@ -149,6 +150,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
   l.ring = o; o += 8 * 3 * c.gmax * c.ring;
   l.red = o; o += 8 * 6 * c.gmax;
   l.ctl = o; o += 1024;
+  l.frc = o; o += 12 * frc_slots;
   l.total = align_up(o, 256);
   return l;
 }
@@ -161,6 +163,11 @@ __host__ __device__ inline LdsLayout lds_layout(int ext, const Caps& c, bool lis
 struct Variant {
   int block, apt, ext, list_lds, wpe, mi, nvt, eam;
 };
+// Whether a launch shape keeps its forces in LDS (the minimum-image shapes
+// with four or more atoms per thread, whose per-atom state outgrows the
+// registers), and the force slots it then needs.
+__host__ __device__ constexpr bool forces_in_lds(bool mi, int apt) { return mi && apt >= 4; }
+inline int frc_slots(const Variant& v) { return forces_in_lds(v.mi != 0, v.apt) ? v.block * v.apt : 0; }
 inline bool same_variant(const Variant& a, const Variant& b) {
   return a.block == b.block && a.apt == b.apt && a.ext == b.ext && a.list_lds == b.list_lds && a.wpe == b.wpe &&
          a.mi == b.mi && a.nvt == b.nvt && a.eam == b.eam;

@@ -66,7 +66,7 @@ bool best_variant(const Ctx& c, const CellPlan& p, const Caps& caps, Variant& ou
   long best = 0;
   for (int i = 0; i < variant_count(); ++i) {
     const Variant v = variant_at(i);
-    const int lds = lds_layout(v.ext, caps, v.list_lds).total;
+    const int lds = lds_layout(v.ext, caps, v.list_lds, frc_slots(v)).total;
     if (v.mi != p.minimg || v.nvt != p.nvt || v.eam != (c.potential == MDEOS_POT_EAM ? 1 : 0) ||
         v.block * v.apt < p.N || v.ext - 1 < p.ext_need || lds > kLdsMax)
       continue;
@@ -160,7 +160,7 @@ mdeos_status Ctx::eval_noalloc(int n, const mdeos_cell_spec* specs, const mdeos_
       set_last_error("mdeos_eval_batch_noalloc: no launch shape holds a group's merged capacities");
       return MDEOS_INVALID_ARG;
     }
-    G.lds = lds_layout(G.v.ext, G.caps, G.v.list_lds).total;
+    G.lds = lds_layout(G.v.ext, G.caps, G.v.list_lds, frc_slots(G.v)).total;
     G.grid = std::max(1, std::min(G.count, std::max(1, occupancy(G.v, G.lds)) * n_cu));
     G.off = off;
     h_work[2 * g] = G.count;

@@ -385,8 +385,9 @@ def main() -> int:
     prec = m.PREC_KAHAN if args.precision == "kahan" else m.PREC_FP64
     specs, sch = m.specs_from_workload(w)
     n = w.n
-    # Verlet skin and inner-list skin (< 0: the walks use the full list), the measured best of each potential
-    skin, inner_skin = (0.5, 0.12) if w.potential == 1 else (0.4, -1.0)
+    # Verlet skin and inner-list skin (< 0: the walks use the full list), the measured best of each
+    # potential; 0 takes the library's per-box-size LJTS default
+    skin, inner_skin = (0.5, 0.12) if w.potential == 1 else (0.0, -1.0)
     ctx = m.mdeos_create(autotune=0 if args.no_autotune else 1, precision=prec, potential=w.potential, skin=skin,
                          prune_skin=inner_skin)
     print(f"# workload {w.name}: {n} cells, {int(w.N.sum())} atoms, {w.sched.n_steps} steps, "
@@ -437,7 +438,7 @@ def main() -> int:
                    "T": [round(float(w.T.min()), 3), round(float(w.T.max()), 3)],
                    "precision_mode": args.precision, "autotune": not args.no_autotune,
                    "potential": "eam (Sutton-Chen 9-6 stand-in)" if w.potential == 1 else "ljts",
-                   "skin": skin, "inner_skin": inner_skin if inner_skin > 0 and args.precision == "fp64" else None,
+                   "skin": skin if skin > 0 else "per box size: 0.3 up to 150 atoms, 0.4 up to 600 or rc > 3.5, 0.6 above", "inner_skin": inner_skin if inner_skin > 0 and args.precision == "fp64" else None,
                    "precision": "fp32 pair forces; fp64 state, energy/virial sums, reductions and re-pin"
                    if args.precision == "fp64" else
                    "fp32 pair forces; Kahan fp32 per-atom energy/virial sums; fp64 state, reductions, re-pin"},

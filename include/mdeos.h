@@ -122,8 +122,10 @@ typedef struct {
 typedef struct {
     int device;                /* HIP device ordinal */
     size_t hbm_budget;         /* bytes of resident cell state the context may hold; 0 = 64 GiB */
-    float skin;                /* Verlet skin; <= 0 selects, per cell, 0.4 (LJTS), or for MDEOS_POT_EAM
-                                  0.5 up to 1000 atoms and 0.3 above */
+    float skin;                /* Verlet skin; <= 0 selects, per cell, the measured best: LJTS 0.3 up
+                                  to 150 atoms, 0.4 up to 600 atoms or for rc > 3.5, 0.6 above (0.4
+                                  if the extended box does not fit at 0.6); MDEOS_POT_EAM 0.5 up to
+                                  1000 atoms and 0.3 above */
     int autotune;              /* 1 = time candidate launch shapes on first use of a bucket */
     const char* tune_cache;    /* JSON file of tuned launch shapes (read and written); NULL = none */
     int precision;             /* how each atom sums its pair energies and virials (forces are FP32):
@@ -184,7 +186,8 @@ const char* mdeos_last_error(void);
 const char* mdeos_version(void);
 /* Validates a query and its schedule; MDEOS_OK or MDEOS_INVALID_ARG. */
 mdeos_status mdeos_validate(const mdeos_cell_spec* spec, const mdeos_schedule* sched);
-/* Plans the device work of one query (capacities, LDS bytes, variant). */
+/* Plans the device work of one query (capacities, LDS bytes, variant) at
+   Verlet skin `skin`; skin <= 0 selects the LJTS default of mdeos_config. */
 mdeos_status mdeos_plan(const mdeos_cell_spec* spec, float skin, mdeos_plan_info* out);
 /* Device bytes one resident cell of n_c holds (used for HBM admission). */
 size_t mdeos_cell_bytes(int n_c);

@@ -107,8 +107,18 @@ static int lattice_neighbours(double l, double rl) {
 // Plans one cell: geometry, capacities and the LDS it needs. Capacities cover
 // the start lattice exactly and the liquid with a margin; a cell that still
 // overflows is re-run with larger capacities by the batch paths.
+//
+// skin <= 0 selects the measured best LJTS skin of the box size (kernel time
+// of the uneven batch's cells of each size at skins 0.3-0.8): 0.3 sigma up to
+// 150 atoms, 0.4 up to 600 atoms and for rc above 3.5 sigma, 0.6 above 600
+// atoms; a box whose extended box does not fit at 0.6 takes 0.4.
 mdeos_status plan_cell(const mdeos_cell_spec& s, float skin, CellPlan& out) {
-  if (skin <= 0.f) skin = 0.4f;
+  if (skin <= 0.f) {
+    const long n = 4L * s.n_c * s.n_c * s.n_c;
+    const float d = n <= 150 ? 0.3f : ((n <= 600 || s.rc > 3.5) ? 0.4f : 0.6f);
+    if (d != 0.4f && plan_cell(s, d, out) == MDEOS_OK) return MDEOS_OK;
+    skin = 0.4f;
+  }
   const double L = box_length(s.n_c, s.rho);
   const double l = std::cbrt(4.0 / s.rho);
   const int N = 4 * s.n_c * s.n_c * s.n_c;

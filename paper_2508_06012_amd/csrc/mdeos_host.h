@@ -119,12 +119,12 @@ struct Ctx {
   // shapes only; the compensated FP32 sums would fold their zero terms
   // differently, so that mode keeps none.
   // Verlet skin of a cell: the caller's, else the measured best of the
-  // potential. 0.4 sigma for LJTS. For the embedded-atom form: 0.5 a up to 1000
-  // atoms, and 0.3 a above, where the ghost-extended boxes at 0.5 outgrow their
-  // launch shapes.
+  // potential. For LJTS, 0 (plan_cell's per-size default). For the
+  // embedded-atom form: 0.5 a up to 1000 atoms, and 0.3 a above, where the
+  // ghost-extended boxes at 0.5 outgrow their launch shapes.
   float cell_skin(const mdeos_cell_spec& s) const {
     if (skin > 0.f) return skin;
-    if (potential != MDEOS_POT_EAM) return 0.4f;
+    if (potential != MDEOS_POT_EAM) return 0.f;
     return 4L * s.n_c * s.n_c * s.n_c <= 1000 ? 0.5f : 0.3f;
   }
   bool prune_lists() const {

@@ -251,7 +251,7 @@ def mdeos_validate(spec: CellSpec, sched: Schedule | None = None) -> int:
     return lib().mdeos_validate(C.byref(spec), C.byref(sched) if sched is not None else None)
 
 
-def mdeos_plan(spec: CellSpec, skin: float = 0.3) -> PlanInfo:
+def mdeos_plan(spec: CellSpec, skin: float = 0.0) -> PlanInfo:
     info = PlanInfo()
     _check(lib().mdeos_plan(C.byref(spec), skin, C.byref(info)), "mdeos_plan")
     return info

@@ -255,6 +255,15 @@ def _short(name: str) -> str:
     return n.split("(")[0] if not n.startswith("at::") else n.split("<")[0]
 
 
+def _advance_steps(items, b):
+    """The advance dispatches of the timed steps, grouped per step: `items` in
+    dispatch order, each (kernel name, ...); the last steps x launches-per-step."""
+    nl = int(b["roofline"].get("advance_launches_per_step", 1))
+    adv = [it for it in items if f"{ADVANCE}<" in it[0]]
+    adv = adv[-b["steps"] * nl:]
+    return [adv[i * nl:(i + 1) * nl] for i in range(b["steps"])], nl
+
+
 def trace_summary(trace_dir: str, bench_json: str, cmd: str) -> str:
     """Kernel-time summary of a `rocprofv3 --kernel-trace --stats` run of bench.py."""
     b = _bench_line(bench_json)
@@ -262,9 +271,12 @@ def trace_summary(trace_dir: str, bench_json: str, cmd: str) -> str:
     trace = _csv_rows(trace_dir, "kernel_trace.csv")
     stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
     top = stats[0]["Name"]
-    disp = sorted((r for r in trace if r["Kernel_Name"] == top), key=lambda r: int(r["Start_Timestamp"]))
-    timed = disp[-b["steps"]:]
-    avg = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in timed) / len(timed) / 1e6
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    items = [(_short(r["Kernel_Name"]) + "<", int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+             for r in trace]
+    steps, nl = _advance_steps(items, b)
+    span = sum(max(e for _, _, e, _ in st) - min(s0 for _, s0, _, _ in st) for st in steps) / len(steps) / 1e6
+    busy = sum(sum(e - s0 for _, s0, e, _ in st) for st in steps) / len(steps) / 1e6
     kms = b["roofline"]["kernel_ms"]
     out = [f"# {_short(top)} on {b['config']['workload']} ({b['config'].get('precision_mode', 'fp64')})", "",
            "Command (from the repository root, on the GPU host):", "", "```",
@@ -275,32 +287,49 @@ def trace_summary(trace_dir: str, bench_json: str, cmd: str) -> str:
     for r in stats[:6]:
         out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f} |")
-    out += ["", f"Timed dispatches of the dominant kernel (the last {len(timed)}): average "
-            f"**{avg:.3f} ms** per launch; bench.py's HIP-event time on the launch stream: "
-            f"**{kms:.3f} ms** (difference {100 * (avg - kms) / kms:+.2f} %).", "",
-            f"Full kernel name: `{top}`", "",
+    if nl == 1:
+        out += ["", f"Timed dispatches of the dominant kernel (the last {len(steps)}): average "
+                f"**{span:.3f} ms** per launch; bench.py's HIP-event time on the launch stream: "
+                f"**{kms:.3f} ms** (difference {100 * (span - kms) / kms:+.2f} %).", ""]
+    else:
+        out += ["", f"Each timed step launches {nl} advance kernels (one per size bucket, on concurrent "
+                f"streams). Over the last {len(steps)} steps: first start to last end **{span:.3f} ms** per "
+                f"step (the sum of the {nl} launch durations, which overlap, is {busy:.1f} ms); bench.py's "
+                f"HIP-event time of the step: **{kms:.3f} ms** (difference {100 * (span - kms) / kms:+.2f} %).",
+                "", "Launches of the last timed step:", "", "| launch shape | ms |", "|---|---|"]
+        for name, s0, e, full in sorted(steps[-1], key=lambda it: -(it[2] - it[1])):
+            shape = full[full.index("<") + 1:full.index(">")] if "<" in full else full
+            out.append(f"| `{shape}` | {(e - s0) / 1e6:.1f} |")
+        out.append("")
+    out += [f"Full name of the kernel with the most time: `{top}`", "",
             f"bench line: value {b['value']} {b['unit']}, roofline achieved {b['roofline']['achieved']} "
             f"{b['roofline']['unit']} (frac {b['roofline']['frac']} of {b['roofline']['peak']}).", ""]
     return "\n".join(out)
 
 
+def _counters(d: str):
+    """Per-dispatch counter sums of a `rocprofv3 --pmc ... --output-format csv` run,
+    in dispatch order: [(kernel name, {counter: value})]."""
+    by = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        e = by.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], {}])
+        e[1][r["Counter_Name"]] = e[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [(by[i][0], by[i][1]) for i in sorted(by)]
+
+
 def pmc_summary(fetch_dir: str, write_dir: str, bench_json: str, cmds: list[str]) -> str:
-    """HBM traffic of the dominant kernel from FETCH_SIZE and WRITE_SIZE passes,
-    each scaled by the same counter's reading for a plain device copy of
-    known size (the last dispatch of the run)."""
+    """HBM traffic of the advance launches of a step from FETCH_SIZE and
+    WRITE_SIZE passes, each scaled by the same counter's reading for a plain
+    device copy of known size (the last dispatch of the run)."""
     b = _bench_line(bench_json)
-    steps = b["steps"]
     copy_bytes = b["copy_calibration"]["bytes"]
     per = {}
     for key, d, cname in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
-        rows = [r for r in _csv_rows(d, "counter_collection.csv") if r["Counter_Name"] == cname]
-        by = {}
-        for r in rows:
-            by.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
-        ids = sorted(by)
-        adv = [by[i][1] for i in ids if f"::{ADVANCE}<" in by[i][0]][-steps:]
-        last = [by[i] for i in ids if "elementwise" in by[i][0]][-1]
-        per[key] = {"advance_kib": sum(adv) / len(adv), "copy_kib": last[1], "copy_kernel": _short(last[0])}
+        disp = _counters(d)
+        steps, nl = _advance_steps([(_short(n) + "<", c.get(cname, 0.0)) for n, c in disp], b)
+        last = [(n, c.get(cname, 0.0)) for n, c in disp if "elementwise" in n][-1]
+        per[key] = {"advance_kib": sum(sum(v for _, v in st) for st in steps) / len(steps), "copy_kib": last[1],
+                    "copy_kernel": _short(last[0])}
     f_fetch = copy_bytes / (per["fetch"]["copy_kib"] * 1024.0)
     f_write = copy_bytes / (per["write"]["copy_kib"] * 1024.0)
     fetch_b = per["fetch"]["advance_kib"] * 1024.0 * f_fetch
@@ -308,22 +337,87 @@ def pmc_summary(fetch_dir: str, write_dir: str, bench_json: str, cmds: list[str]
     traffic = fetch_b + write_b
     kms = b["roofline"]["kernel_ms"]
     algo = b["roofline"].get("state_bytes_per_launch")
+    unit = "launch" if nl == 1 else f"step ({nl} launches)"
     out = [f"# HBM traffic of {ADVANCE} on {b['config']['workload']} ({b['config'].get('precision_mode', 'fp64')})",
            "", "Commands (from the repository root, on the GPU host):", "", "```",
            "cd /tmp && export TMPDIR=/tmp && cd -", *cmds, "```", "",
            f"Calibration: the last dispatch of each run is a plain device copy (`{per['fetch']['copy_kernel']}`) "
            f"of {copy_bytes} bytes read and written; factors known bytes / counter bytes: "
            f"FETCH {f_fetch:.4f}, WRITE {f_write:.4f}.", "",
-           f"Per {ADVANCE} launch (mean of the {steps} timed dispatches):", "",
-           "| counter | KiB per launch | calibrated bytes | GB/s at the event-timed duration |",
+           f"Per {unit}, mean of the {b['steps']} timed steps:", "",
+           "| counter | KiB | calibrated bytes | GB/s at the event-timed duration |",
            "|---|---|---|---|",
            f"| FETCH_SIZE | {per['fetch']['advance_kib']:.4g} | {fetch_b:.4g} | {fetch_b / kms / 1e6:.1f} |",
            f"| WRITE_SIZE | {per['write']['advance_kib']:.4g} | {write_b:.4g} | {write_b / kms / 1e6:.1f} |",
-           "", f"Kernel duration (bench.py, HIP events): {kms:.3f} ms.",
-           f"Algorithmic bytes per launch (every atom's state read once and written once): {algo:.4g}." if algo else "",
+           "", f"Kernel duration (bench.py, HIP events): {kms:.3f} ms" +
+           ("." if nl == 1 else " (under counter collection the launches of a step run one after another)."),
+           f"Algorithmic bytes (every atom's state read once and written once): {algo:.4g}." if algo else "",
            "", "Read by bench.py (roofline.traffic) while the kernel sources are unchanged:", "",
            f"- `traffic_bytes_per_launch`: {traffic:.6e}",
            f"- `kernel_sources_sha256`: `{kernel_sources_sha256()}`", ""]
+    return "\n".join(out)
+
+
+VALU_PASSES = (
+    ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
+     "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_FLOPS_FP32", "SQ_THREAD_CYCLES_VALU", "SQ_BUSY_CYCLES"),
+    ("SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "SQ_WAVE_CYCLES",
+     "SQ_WAVES", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_SALU"),
+)
+
+
+def valu_summary(dirs: list[str], bench_json: str, cmds: list[str]) -> str:
+    """VALU and LDS counters of the advance launches of a step (two --pmc
+    passes of VALU_PASSES), with the executed FP32 FLOP rate next to the
+    algorithmic one."""
+    b = _bench_line(bench_json)
+    tot = {}
+    nl = 1
+    for d in dirs:
+        disp = _counters(d)
+        steps, nl = _advance_steps([(_short(n) + "<", c) for n, c in disp], b)
+        for st in steps:
+            for _, c in st:
+                for k, v in c.items():
+                    tot[k] = tot.get(k, 0.0) + v / len(steps)
+    kms = b["roofline"]["kernel_ms"]
+    t = kms / 1e3
+    cus, clk = 256, 2.4e9
+    atom_steps = b["atom_steps_per_s"] * b["ms_per_step"] / 1e3
+    iv = tot["SQ_INSTS_VALU"]
+    flops32 = 64.0 * tot["SQ_INSTS_VALU_FLOPS_FP32"]
+    lanes = tot["SQ_THREAD_CYCLES_VALU"] / iv
+    unit = "launch" if nl == 1 else f"step ({nl} launches)"
+    out = [f"# VALU and LDS counters of {ADVANCE} on {b['config']['workload']} "
+           f"({b['config'].get('precision_mode', 'fp64')})", "",
+           "Commands (from the repository root, on the GPU host):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp && cd -", *cmds, "```", "",
+           f"Counters summed over the advance dispatches of one {unit}, mean of the {b['steps']} timed steps "
+           "(instruction counters count wave-wide instructions):", "",
+           "| counter | value |", "|---|---|"]
+    for k in [c for p in VALU_PASSES for c in p]:
+        if k in tot:
+            out.append(f"| {k} | {tot[k]:.4g} |")
+    out += ["", f"Derived, with the event-timed duration {kms:.3f} ms of the bench line given (a run without "
+            f"counter collection), {cus} CUs at {clk / 1e9:.1f} GHz and "
+            f"{atom_steps:.4g} atom-steps per step:", "",
+            f"- VALU lane-instructions per atom-step: {64 * iv / atom_steps:.0f}",
+            f"- VALU wave-instructions issued per CU and clock: {iv / (cus * clk * t):.3f} (a register-only "
+            "v_fma_f32 loop reaches 1.57)",
+            f"- active lanes per VALU instruction (SQ_THREAD_CYCLES_VALU / SQ_INSTS_VALU): {lanes:.1f} of 64",
+            f"- FP32 instructions per VALU instruction: FMA {tot['SQ_INSTS_VALU_FMA_F32'] / iv:.3f}, "
+            f"MUL {tot['SQ_INSTS_VALU_MUL_F32'] / iv:.3f}, ADD {tot['SQ_INSTS_VALU_ADD_F32'] / iv:.3f}, "
+            f"TRANS {tot['SQ_INSTS_VALU_TRANS_F32'] / iv:.3f}",
+            f"- executed FP32 FLOP/s (64 x SQ_INSTS_VALU_FLOPS_FP32 / duration): {flops32 / t / 1e12:.2f} TFLOP/s; "
+            f"weighted by the active lanes: {flops32 * lanes / 64 / t / 1e12:.2f} TFLOP/s",
+            f"- algorithmic FP32 FLOP/s (bench.py: {b['roofline']['flop_per_pair']} FLOP per in-range pair): "
+            f"{b['roofline']['achieved']:.2f} TFLOP/s, frac {b['roofline']['frac']} of {b['roofline']['peak']}"]
+    if "SQ_INSTS_LDS" in tot:
+        out += [f"- LDS instructions per atom-step (wave-wide): {tot['SQ_INSTS_LDS'] / atom_steps:.3f}; "
+                f"bank-conflict cycles per LDS instruction: {tot['SQ_LDS_BANK_CONFLICT'] / tot['SQ_INSTS_LDS']:.2f}; "
+                f"bank-conflict cycles per CU over the duration: "
+                f"{tot['SQ_LDS_BANK_CONFLICT'] / cus / (clk * t):.2f} of each cycle"]
+    out.append("")
     return "\n".join(out)
 
 
@@ -350,13 +444,24 @@ def main() -> int:
                     help="write a markdown summary of a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_LOG"),
                     help="write a markdown summary of FETCH_SIZE / WRITE_SIZE runs and exit")
+    ap.add_argument("--valu-summary", nargs=3, metavar=("PASS1_DIR", "PASS2_DIR", "BENCH_LOG"),
+                    help="write a markdown summary of the two VALU / LDS counter passes and exit")
+    ap.add_argument("--valu-pass", type=int, default=0, choices=[1, 2],
+                    help="print the --pmc counter list of that VALU pass and exit")
     ap.add_argument("--cmd", action="append", default=[], help="command lines recorded in a summary")
     ap.add_argument("--out", default=None, help="summary file (default: stdout)")
     args = ap.parse_args()
 
-    if args.trace_summary or args.pmc_summary:
-        text = (trace_summary(*args.trace_summary, " && ".join(args.cmd)) if args.trace_summary
-                else pmc_summary(*args.pmc_summary, args.cmd))
+    if args.valu_pass:
+        print(" ".join(VALU_PASSES[args.valu_pass - 1]))
+        return 0
+    if args.trace_summary or args.pmc_summary or args.valu_summary:
+        if args.trace_summary:
+            text = trace_summary(*args.trace_summary, " && ".join(args.cmd))
+        elif args.pmc_summary:
+            text = pmc_summary(*args.pmc_summary, args.cmd)
+        else:
+            text = valu_summary(args.valu_summary[:2], args.valu_summary[2], args.cmd)
         if args.out:
             with open(args.out, "w") as f:
                 f.write(text)
@@ -395,13 +500,14 @@ def main() -> int:
     for i in range(args.warmup):
         m.mdeos_eval_batch(ctx, specs, sch)
         print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    kernel_ms = []
+    kernel_ms, launches = [], []
     sync()
     t0 = time.perf_counter()
     for i in range(args.steps):
         res = m.mdeos_eval_batch(ctx, specs, sch)
         ms, nl = m.mdeos_last_advance_time(ctx)
         kernel_ms.append(ms)
+        launches.append(nl)
         print(f"# step {i + 1}/{args.steps}: advance {ms:.1f} ms in {nl} launch(es)", file=sys.stderr, flush=True)
     sync()
     wall = time.perf_counter() - t0
@@ -419,8 +525,8 @@ def main() -> int:
     traffic = traffic_from_profile(args.workload, args.precision)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
-
             "kernel_ms": round(float(np.mean(kernel_ms)), 3), "flops_per_launch": flops,
+            "advance_launches_per_step": int(max(launches)),
             "flop_per_pair": fp, "flop_per_pair_energy_step": fp + fpe,
             "pairs_per_atom_step": float(np.sum(res["pairs"]) / np.sum(w.N)),
             "state_bytes_per_launch": float(2 * 72 * np.sum(w.N))}

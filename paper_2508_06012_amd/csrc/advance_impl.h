@@ -1573,23 +1573,35 @@ struct Box {
 
   // --- the cell -----------------------------------------------------------------------
 
+  // Advances cell cidx from where it stands: a cell not yet lifted is lifted
+  // first (its state and accumulators then stored as at step 0), and the
+  // steps always start from the stored state, as after a chunk boundary, so
+  // the kernel holds one copy of the step loop and a whole run takes the path
+  // of a chunked one.
   DEVI void run(int cidx) {
     load_cell(cidx);
     const int phase = c->phase;
     if (phase == PH_DONE) return;
-    if (phase == PH_RUN) {
-      const int step = c->step;
-      load_acc();
-      load_state();
+    if (phase != PH_RUN) {
+      if (!lift_cell(phase) || p.step_budget < 0) return;  // (a lift-only launch ends here)
       __syncthreads();
-      if (!build_lists()) {
-        fail_overflow(step);
-        return;
-      }
-      refresh_positions();
-      advance_steps(step);
+      if (c->phase != PH_RUN) return;
+    }
+    const int step = c->step;
+    load_acc();
+    load_state();
+    __syncthreads();
+    if (!build_lists()) {
+      fail_overflow(step);
       return;
     }
+    refresh_positions();
+    advance_steps(step);
+  }
+
+  // Lifting operator and the forces-only pass; false when the cell failed or
+  // is done (nothing left to advance in this launch).
+  DEVI bool lift_cell(int phase) {
     clear_acc();
     __syncthreads();
     double Ec = 0.0, U0 = 0.0, W0 = 0.0;
@@ -1597,7 +1609,7 @@ struct Box {
       load_state();
       if (!full_force_pass(U0, W0)) {
         fail_overflow(0);
-        return;
+        return false;
       }
 #pragma unroll
       for (int k = 0; k < APT; ++k) vx[k] = vy[k] = vz[k] = 0.0;
@@ -1609,13 +1621,13 @@ struct Box {
         c->phase = PH_DONE;
         c->status = 0;
       }
-      return;
+      return false;
     }
     // lifting operator: E_cold of the static lattice at rho
     lattice_positions(c->rho);
     if (!full_force_pass(Ec, W0)) {
       fail_overflow(0);
-      return;
+      return false;
     }
     if (t == 0) c->Ecold = Ec;
     Ecold = Ec;
@@ -1639,7 +1651,7 @@ struct Box {
       __syncthreads();
       if (!full_force_pass(U0, W0)) {
         fail_overflow(0);
-        return;
+        return false;
       }
       if (phase == PH_WARM && !(fma((double)N, c->e, -(U0 - Ec)) > 0.0)) {
         // no kinetic energy left above the new cold lattice: lift cold instead
@@ -1648,13 +1660,17 @@ struct Box {
         lattice_positions(c->rho);
         if (!full_force_pass(U0, W0)) {
           fail_overflow(0);
-          return;
+          return false;
         }
       }
     }
     if (cold) draw_velocities();
     record_step0(U0, W0);
-    advance_steps(0);
+    // the state after the lift, as a launch that stops at step 0 leaves it
+    store_state();
+    const bool done = n_steps <= 0 || ctl->stop != 0;
+    store_acc(0, done ? PH_DONE : PH_RUN);
+    return !done;
   }
 
   DEVI void fail_overflow(int step) {

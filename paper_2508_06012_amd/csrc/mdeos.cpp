@@ -347,6 +347,7 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
   }
   load_tune_cache();
   if (const char* sc = getenv("MDEOS_SHRINK_CAPS")) shrink_caps = atoi(sc) != 0;
+  if (const char* tl = getenv("MDEOS_TUNE_LOG")) tune_log = atoi(tl) != 0;
   if (const char* fv = getenv("MDEOS_FORCE_VARIANT")) {
     Variant v{};
     const int nf = sscanf(fv, "%d,%d,%d,%d,%d,%d,%d,%d", &v.block, &v.apt, &v.ext, &v.list_lds, &v.wpe, &v.mi,
@@ -682,8 +683,8 @@ bool Ctx::choose_variant(const CellPlan& p, Variant& out) const {
 // timed on successive chunks of the batch's own work and nothing is
 // recomputed: one untimed chunk (lift and the first steps), then kTuneRounds
 // rounds of one kTuneSteps chunk per candidate, the bucket alone on the
-// device. The fastest (minimum over rounds) is kept under the bucket's tune
-// key and written to the tune cache.
+// device. The fastest (mean over rounds) is kept under the bucket's tune key
+// and written to the tune cache.
 static constexpr int kTuneSteps = 40, kTuneRounds = 2, kTuneMaxCand = 6, kTuneMinCells = 64;
 
 mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) {
@@ -711,19 +712,36 @@ mdeos_status Ctx::autotune_buckets(std::vector<Bucket>& buckets, hipStream_t s) 
     use(b.v);
     mdeos_status st = run_buckets(one, kTuneSteps, s, false);
     if (st != MDEOS_OK) return st;
-    std::vector<float> best(cand.size(), 1e30f);
+    // A candidate is judged by the time of its steps: a chunk of kTuneSteps
+    // steps minus a chunk of none, which costs what every chunk pays once
+    // (loading the state, rebuilding the lists, storing) and which a whole
+    // run pays only once. The cells keep evolving while they are timed (a
+    // lattice melting, the rebuild rate settling), so a chunk costs more or
+    // less depending on when it runs: rounds alternate the candidate order
+    // (forward, then backward) and each candidate takes its mean over the
+    // rounds, so a cost that drifts linearly adds the same to every candidate.
+    auto timed = [&](int budget, float& ms) {
+      mdeos_status e2 = run_buckets(one, budget, s, false);
+      if (e2 != MDEOS_OK) return e2;
+      if (hipEventSynchronize(ev_t1) != hipSuccess || hipEventElapsedTime(&ms, ev_t0, ev_t1) != hipSuccess)
+        return set_error("tuning timer failed"), MDEOS_DEVICE_ERROR;
+      return MDEOS_OK;
+    };
+    std::vector<double> mean(cand.size(), 0.0);
     for (int r = 0; r < kTuneRounds; ++r) {
-      for (size_t i = 0; i < cand.size(); ++i) {
+      for (size_t j = 0; j < cand.size(); ++j) {
+        const size_t i = (r & 1) ? cand.size() - 1 - j : j;
         use(cand[i]);
-        st = run_buckets(one, kTuneSteps, s, false);
-        if (st != MDEOS_OK) return st;
-        HCHECK(hipEventSynchronize(ev_t1));
-        float ms = 0.f;
-        HCHECK(hipEventElapsedTime(&ms, ev_t0, ev_t1));
-        best[i] = std::min(best[i], ms);
+        float t_none = 0.f, t_steps = 0.f;
+        if ((st = timed(-1, t_none)) != MDEOS_OK || (st = timed(kTuneSteps, t_steps)) != MDEOS_OK) return st;
+        mean[i] += (double)(t_steps - t_none) / kTuneRounds;
+        if (tune_log)
+          fprintf(stderr, "[mdeos tune] %s round %d: %d,%d,%d,%d,%d,%d,%d,%d no steps %.3f ms, %d steps %.3f ms\n",
+                  key.c_str(), r, cand[i].block, cand[i].apt, cand[i].ext, cand[i].list_lds, cand[i].wpe,
+                  cand[i].mi, cand[i].nvt, cand[i].eam, t_none, kTuneSteps, t_steps);
       }
     }
-    const size_t w = std::min_element(best.begin(), best.end()) - best.begin();
+    const size_t w = std::min_element(mean.begin(), mean.end()) - mean.begin();
     tuned[key] = cand[w];
     changed = true;
     b.v = cand[w];

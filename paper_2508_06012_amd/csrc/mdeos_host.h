@@ -172,6 +172,7 @@ struct Ctx {
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, Variant> tuned;
   Variant forced_variant{0, 0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe,mi" (tuning)
+  bool tune_log = false;  // MDEOS_TUNE_LOG=1: the autotuner prints each candidate's timings to stderr
   // MDEOS_SHRINK_CAPS=1: eval_batch / eval_plain plan every cell with an
   // 8-entry neighbour list, so the first list build overflows and their
   // capacity retry runs (a test hook: capacities never change a cell's

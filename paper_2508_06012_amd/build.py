@@ -20,8 +20,8 @@ LIB = os.path.join(HERE, "libmdeos.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["advance_a.hip", "advance_b.hip", "advance_c.hip", "advance_d.hip", "advance_e.hip", "advance_f.hip",
-           "advance_g.hip", "advance_h.hip", "advance_g2.hip", "advance_h2.hip", "kernels.hip", "mdeos.cpp",
-           "serve.cpp", "noalloc.hip"]
+           "advance_g.hip", "advance_h.hip", "advance_g2.hip", "advance_h2.hip", "advance_i.hip", "advance_j.hip",
+           "kernels.hip", "mdeos.cpp", "serve.cpp", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

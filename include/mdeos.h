@@ -26,6 +26,13 @@
  *     MDEOS_OK even when some cells failed.
  *   - A context is used by one thread at a time, except the serving calls,
  *     which are thread-safe.
+ *
+ * Diagnostic environment switches, read when a context is created:
+ *   MDEOS_FORCE_VARIANT="block,apt,ext,list_lds,wpe,mi[,nvt,eam]" runs every
+ *     bucket the shape fits with that launch shape (no tuning);
+ *   MDEOS_TUNE_LOG=1 prints the autotuner's timings to stderr;
+ *   MDEOS_SHRINK_CAPS=1 plans every cell with a tiny neighbour capacity, so
+ *     the batch paths' capacity retry runs.
  */
 #ifndef MDEOS_H
 #define MDEOS_H

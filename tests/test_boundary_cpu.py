@@ -70,6 +70,18 @@ def test_valid_workload_cells_plan():
             assert p.ext_cap >= p.N
 
 
+def test_default_skin_per_box_size():
+    """skin <= 0 plans with the per-size LJTS default: 0.3 up to 150 atoms, 0.4
+    up to 600 atoms or for rc > 3.5, 0.6 above."""
+    cases = [(3, 0.8, 2.5, 0.3), (4, 0.8, 2.5, 0.4), (5, 0.8, 2.5, 0.4), (6, 0.8, 2.5, 0.6), (7, 0.8, 3.0, 0.6),
+             (10, 0.8, 2.5, 0.6), (6, 0.8, 4.0, 0.4)]
+    for n_c, rho, rc, skin in cases:
+        s = spec(rho=rho, n_c=n_c, rc=rc)
+        p = m.mdeos_plan(s, 0.0)
+        assert p.rl == pytest.approx(rc + skin, abs=1e-6), (n_c, rho, rc, p.rl)
+        assert m.mdeos_plan(s, skin).ext_cap == p.ext_cap
+
+
 def test_multi_image_flagged():
     p = m.mdeos_plan(spec(rho=1.2, n_c=3, rc=3.0))
     assert p.multi_image == 1

@@ -67,3 +67,23 @@ def test_every_launch_shape_gives_the_same_bits(name, potential, ensemble, state
     for v in shapes[1:]:
         got = run_forced(v, potential, specs, sch, skin)
         assert got.tobytes() == ref.tobytes(), v
+
+
+def test_every_minimum_image_shape_gives_the_same_bits():
+    """The minimum-image shapes on 2048-atom boxes (dense, rc 3.0, which plan as
+    minimum image): 2 to 8 atoms per thread, 512 or 1024 threads, forces in
+    registers (2 atoms per thread) or in LDS (4 and more)."""
+    n_c, rho, rc, skin = 8, 1.1, 3.0, 0.6
+    specs = m.make_specs(np.full(3, rho), 1.5, n_c, rc, 0.004, np.arange(7, 10), np.arange(3))
+    plan = m.mdeos_plan(specs[0], skin)
+    assert plan.ext_cap == 4087  # minimum image
+    sch = m.make_schedule(120, 60, (40,), 10, 10)
+    shapes = [v for v in shape_table() if v[5] == 1 and v[6] == 0 and v[7] == 0 and v[0] * v[1] >= plan.N]
+    assert len(shapes) >= 4, shapes
+    print(f"minimum image: {len(shapes)} launch shapes", flush=True)
+    ref = run_forced(shapes[0], 0, specs, sch, skin)
+    assert not (ref["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)).any()
+    for v in shapes[1:]:
+        print(f"  shape {v}", flush=True)
+        got = run_forced(v, 0, specs, sch, skin)
+        assert got.tobytes() == ref.tobytes(), v

@@ -202,6 +202,7 @@ void Ctx::serve_loop() {
   const hipStream_t s = own_stream;
   std::deque<ServeQuery> waiting;  // arrival order
   std::vector<Active> active;
+  std::vector<Active> pending;     // admitted while a chunk ran; in the next one
   long long round = 0;
   size_t resident_bytes = 0;
   long long resident = 0;
@@ -214,7 +215,7 @@ void Ctx::serve_loop() {
     bool stop = false, drain = true;
     {
       std::unique_lock<std::mutex> lk(serve_mu);
-      if (active.empty() && waiting.empty() && serve_queue.empty() && !serve_stop_flag)
+      if (active.empty() && pending.empty() && waiting.empty() && serve_queue.empty() && !serve_stop_flag)
         serve_cv.wait_for(lk, std::chrono::milliseconds(2));
       while (!serve_queue.empty()) {
         waiting.push_back(serve_queue.front());
@@ -225,92 +226,101 @@ void Ctx::serve_loop() {
       serve_stats.queued = (long long)waiting.size();
     }
     if (stop && !drain) finish_all(true);
-    if (stop && waiting.empty() && active.empty()) break;
-    if (stop && !drain && active.empty()) break;
+    if (stop && waiting.empty() && active.empty() && pending.empty()) break;
+    if (stop && !drain && active.empty() && pending.empty()) break;
 
     std::lock_guard<std::recursive_mutex> g(mu);
     ++round;
-    // ---- admission -----------------------------------------------------
-    std::vector<int> upload;
-    const size_t max_active = cfg.max_slots > 0 ? (size_t)cfg.max_slots : (size_t)1 << 30;
-    for (auto it = waiting.begin(); it != waiting.end() && active.size() < max_active;) {
-      ServeCell& sc = serve_cells[it->cell_id];
-      if (sc.busy) {
-        ++it;
-        continue;
-      }
-      const ServeQuery q = *it;
-      mdeos_cell_spec sp{q.rho, q.e, q.n_c, cfg.rc, cfg.dt, cfg.seed, q.cell_id};
-      CellPlan p;
-      const mdeos_status pst = plan_cell(sp, cell_skin(sp), p);
-      p.nvt = cfg.warm.ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;  // used by warm starts (cold ones re-plan)
-      if (pst != MDEOS_OK) {
-        ServeDone d{q.ticket, {}, mono_now() - serve_t0};
-        d.res.status = MDEOS_CELL_OVERFLOW;
-        d.res.P = d.res.T = NAN;
-        std::lock_guard<std::mutex> lk(serve_mu);
-        serve_done.push_back(d);
-        serve_stats.completed += 1;
-        it = waiting.erase(it);
-        continue;
-      }
-      bool warm = sc.slot >= 0 && h_cells[sc.slot].n_c == q.n_c;
-      if (sc.slot >= 0 && !warm) {
-        resident_bytes -= mdeos_cell_bytes(h_cells[sc.slot].n_c);
-        resident -= 1;
-        free_cells({sc.slot});
-        sc.slot = -1;
-      }
-      if (!warm) {
-        const size_t need = mdeos_cell_bytes(q.n_c);
-        // evict idle resident cells, least recently used first
-        while (resident_bytes + need > hbm_budget) {
-          long long victim = -1, oldest = 1LL << 62;
-          for (auto& kv : serve_cells)
-            if (kv.second.slot >= 0 && !kv.second.busy && kv.first != q.cell_id && kv.second.last_use < oldest) {
-              oldest = kv.second.last_use;
-              victim = kv.first;
-            }
-          if (victim < 0) break;
-          ServeCell& vc = serve_cells[victim];
-          resident_bytes -= mdeos_cell_bytes(h_cells[vc.slot].n_c);
-          resident -= 1;
-          free_cells({vc.slot});
-          vc.slot = -1;
-          serve_stats.evictions += 1;
+    // Admits waiting queries into `into`, in arrival order, as slots and
+    // memory allow (a query whose plan fails is answered at once).
+    auto admit = [&](std::vector<Active>& into) {
+      const size_t max_active = cfg.max_slots > 0 ? (size_t)cfg.max_slots : (size_t)1 << 30;
+      for (auto it = waiting.begin(); it != waiting.end() && active.size() + into.size() < max_active;) {
+        ServeCell& sc = serve_cells[it->cell_id];
+        if (sc.busy) {
+          ++it;
+          continue;
         }
-        if (resident_bytes + need > hbm_budget) break;  // wait for capacity
-        std::vector<int> idx;
-        if (alloc_cells(1, &sp, cfg.cold, idx) != MDEOS_OK) break;
-        sc.slot = idx[0];
-        resident_bytes += need;
-        resident += 1;
-      } else {
-        CellRec& r = h_cells[sc.slot];
-        const double Lold = r.Lw;
-        const int off = r.atom_off, query = r.query;
-        fill_record(r, sp, cfg.warm, p, off);
-        r.warm_scale = p.Lw / Lold;
-        r.query = query + 1;
-        r.phase = PH_WARM;
-        cell_plan[sc.slot] = p;
+        const ServeQuery q = *it;
+        mdeos_cell_spec sp{q.rho, q.e, q.n_c, cfg.rc, cfg.dt, cfg.seed, q.cell_id};
+        CellPlan p;
+        const mdeos_status pst = plan_cell(sp, cell_skin(sp), p);
+        p.nvt = cfg.warm.ensemble == MDEOS_NVT_LANGEVIN ? 1 : 0;  // used by warm starts (cold ones re-plan)
+        if (pst != MDEOS_OK) {
+          ServeDone d{q.ticket, {}, mono_now() - serve_t0};
+          d.res.status = MDEOS_CELL_OVERFLOW;
+          d.res.P = d.res.T = NAN;
+          std::lock_guard<std::mutex> lk(serve_mu);
+          serve_done.push_back(d);
+          serve_stats.completed += 1;
+          it = waiting.erase(it);
+          continue;
+        }
+        bool warm = sc.slot >= 0 && h_cells[sc.slot].n_c == q.n_c;
+        if (sc.slot >= 0 && !warm) {
+          resident_bytes -= mdeos_cell_bytes(h_cells[sc.slot].n_c);
+          resident -= 1;
+          free_cells({sc.slot});
+          sc.slot = -1;
+        }
+        if (!warm) {
+          const size_t need = mdeos_cell_bytes(q.n_c);
+          // evict idle resident cells, least recently used first
+          while (resident_bytes + need > hbm_budget) {
+            long long victim = -1, oldest = 1LL << 62;
+            for (auto& kv : serve_cells)
+              if (kv.second.slot >= 0 && !kv.second.busy && kv.first != q.cell_id && kv.second.last_use < oldest) {
+                oldest = kv.second.last_use;
+                victim = kv.first;
+              }
+            if (victim < 0) break;
+            ServeCell& vc = serve_cells[victim];
+            resident_bytes -= mdeos_cell_bytes(h_cells[vc.slot].n_c);
+            resident -= 1;
+            free_cells({vc.slot});
+            vc.slot = -1;
+            serve_stats.evictions += 1;
+          }
+          if (resident_bytes + need > hbm_budget) break;  // wait for capacity
+          std::vector<int> idx;
+          if (alloc_cells(1, &sp, cfg.cold, idx) != MDEOS_OK) break;
+          sc.slot = idx[0];
+          resident_bytes += need;
+          resident += 1;
+        } else {
+          CellRec& r = h_cells[sc.slot];
+          const double Lold = r.Lw;
+          const int off = r.atom_off, query = r.query;
+          fill_record(r, sp, cfg.warm, p, off);
+          r.warm_scale = p.Lw / Lold;
+          r.query = query + 1;
+          r.phase = PH_WARM;
+          cell_plan[sc.slot] = p;
+        }
+        sc.busy = true;
+        sc.last_use = round;
+        const mdeos_schedule& qs = warm ? cfg.warm : cfg.cold;
+        into.push_back(Active{sc.slot, q.cell_id, q.ticket, qs.n_steps, 0, !warm});
+        {
+          std::lock_guard<std::mutex> lk(serve_mu);
+          if (warm) serve_stats.warm += 1;
+          else serve_stats.cold += 1;
+        }
+        it = waiting.erase(it);
       }
-      sc.busy = true;
-      sc.last_use = round;
-      const mdeos_schedule& qs = warm ? cfg.warm : cfg.cold;
-      active.push_back(Active{sc.slot, q.cell_id, q.ticket, qs.n_steps, 0, !warm});
-      upload.push_back(sc.slot);
-      {
-        std::lock_guard<std::mutex> lk(serve_mu);
-        if (warm) serve_stats.warm += 1;
-        else serve_stats.cold += 1;
-      }
-      it = waiting.erase(it);
-    }
+    };
+    // ---- admission: the queries admitted while the last chunk ran, then the
+    // ones that arrived since; their records go up before the launch
+    std::vector<Active> fresh;
+    fresh.swap(pending);
+    admit(fresh);
+    std::vector<int> upload;
+    for (const Active& a : fresh) upload.push_back(a.slot);
     if (!upload.empty() && upload_records(upload, s) != MDEOS_OK) {
       fprintf(stderr, "mdeos serve: record upload failed: %s\n", mdeos_last_error());
       break;
     }
+    active.insert(active.end(), fresh.begin(), fresh.end());
     if (active.empty()) continue;
 
     // ---- one chunk for every admitted cell ------------------------------
@@ -323,6 +333,18 @@ void Ctx::serve_loop() {
       fprintf(stderr, "mdeos serve: launch failed: %s\n", mdeos_last_error());
       break;
     }
+    // while the chunk runs: take the queries that arrived meanwhile and plan
+    // their admission (host work that would otherwise leave the device idle
+    // between chunks); they join the next chunk
+    {
+      std::lock_guard<std::mutex> lk(serve_mu);
+      while (!serve_queue.empty()) {
+        waiting.push_back(serve_queue.front());
+        serve_queue.pop_front();
+      }
+      serve_stats.queued = (long long)waiting.size();
+    }
+    admit(pending);
     double atom_steps = 0.0;
     std::vector<int> finished;
     std::vector<size_t> fin_pos;

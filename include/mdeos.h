@@ -340,7 +340,8 @@ typedef struct {
     double atom_steps;         /* MD atom-steps executed */
 } mdeos_serve_stats;
 
-/* Starts the scheduler thread. */
+/* Starts the scheduler thread. Cells left resident by an earlier session
+ * (a stop keeps them) are released first: every session starts cold. */
 mdeos_status mdeos_serve_start(mdeos_ctx* ctx, const mdeos_serve_config* cfg);
 /* Queues one EOS query for cell `cell_id` at time t_arrival (seconds on the
  * caller's clock, see mdeos_serve_now). Queries of one cell run in order,

@@ -94,8 +94,16 @@ extern "C" mdeos_status mdeos_serve_start(mdeos_ctx* ctx, const mdeos_serve_conf
   if (mdeos_validate(&probe, &cfg->cold) != MDEOS_OK || mdeos_validate(&probe, &cfg->warm) != MDEOS_OK)
     return MDEOS_INVALID_ARG;
   if (!sched_has0(cfg->warm)) return MDEOS_INVALID_ARG;
+  // the context lock first, as the scheduler thread takes them
+  std::lock_guard<std::recursive_mutex> g(c->mu);
   std::lock_guard<std::mutex> lk(c->serve_mu);
   if (c->serving) return MDEOS_INVALID_ARG;
+  // the resident cells of an earlier session stay until now (a stop keeps
+  // them); this session starts with none, so they are released here
+  std::vector<int> idx;
+  for (auto& kv : c->serve_cells)
+    if (kv.second.slot >= 0) idx.push_back(kv.second.slot);
+  c->free_cells(idx);
   c->serve_cfg = *cfg;
   c->serve_stop_flag = false;
   c->serve_drain = true;

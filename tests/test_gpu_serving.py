@@ -189,3 +189,59 @@ def test_staggered_arrivals_equal_alone_bitwise():
                 assert r.tobytes() == ref[k].tobytes(), (c, k)
     finally:
         m.mdeos_destroy(ctx)
+
+
+def test_restart_releases_the_last_sessions_resident_cells():
+    """A stopped session leaves its cells resident; the next start releases
+    them. With room for about three resident cells, a second session of the
+    same three-cell query set completes (it would wait for capacity forever if
+    the first session's cells still held the budget) and gives the same bits."""
+    budget = 3 * m.mdeos_cell_bytes(5) + 4096
+    ctx = m.mdeos_create(hbm_budget=budget)
+    try:
+        qs = queries(n_cells=3, per_cell=2, seed=5)
+        t1, got1, st1 = serve_all(ctx, qs, 50, timeout=60.0)
+        assert len(got1) == len(qs), st1
+        t2, got2, st2 = serve_all(ctx, qs, 50, timeout=60.0)
+        assert len(got2) == len(qs), st2
+        for a, b in zip(t1, t2):
+            assert got1[a].tobytes() == got2[b].tobytes()
+    finally:
+        m.mdeos_destroy(ctx)
+
+
+def test_stop_without_drain_while_chunks_run():
+    """Stopping without draining while chunks are queued on the device: the
+    queries not yet admitted are dropped, the admitted ones finish, and every
+    delivered result is bitwise that of its cell's query prefix run alone."""
+    ctx = m.mdeos_create()
+    try:
+        qs = queries(n_cells=8, per_cell=3, seed=9)
+        m.mdeos_serve_start(ctx, sched(COLD), sched(WARM), RC, DT, SEED, chunk_steps=25)
+        tickets = [m.mdeos_serve_submit(ctx, c, rho, e, n_c, m.mdeos_serve_now(ctx)) for c, rho, e, n_c in qs]
+        t0 = time.time()
+        while m.mdeos_serve_stats_get(ctx)["chunks"] < 3 and time.time() - t0 < 30.0:
+            time.sleep(0.002)
+        m.mdeos_serve_stop(ctx, drain=False)
+        stats = m.mdeos_serve_stats_get(ctx)
+        tk, res, _ = m.mdeos_serve_poll(ctx, 1024)
+        got = {int(k): r for k, r in zip(tk, res)}
+        print(f"  delivered {len(got)} of {len(qs)} after {stats['chunks']} chunks", flush=True)
+        assert stats["active"] == 0
+        assert 0 < len(got) <= len(qs)
+        assert set(got) <= set(tickets)
+        for c in range(8):
+            seq = [q for q in qs if q[0] == c]
+            tk_c = [t for t, q in zip(tickets, qs) if q[0] == c]
+            done = [t in got for t in tk_c]
+            k = sum(done)
+            assert done == [True] * k + [False] * (len(seq) - k), (c, done)  # a cell's queries run in order
+            if k == 0:
+                continue
+            ref = alone(ctx, c, seq[:k])
+            for j in range(k):
+                r = got[tk_c[j]]
+                assert r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) == 0
+                assert r.tobytes() == ref[j].tobytes(), (c, j)
+    finally:
+        m.mdeos_destroy(ctx)

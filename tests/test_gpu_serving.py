@@ -37,8 +37,8 @@ def queries(n_cells=6, per_cell=3, seed=1):
     return out
 
 
-def serve_all(ctx, qs, chunk, timeout=90.0, rc=RC, dt=DT):
-    m.mdeos_serve_start(ctx, sched(COLD), sched(WARM), rc, dt, SEED, chunk_steps=chunk)
+def serve_all(ctx, qs, chunk, timeout=90.0, rc=RC, dt=DT, max_slots=0):
+    m.mdeos_serve_start(ctx, sched(COLD), sched(WARM), rc, dt, SEED, chunk_steps=chunk, max_slots=max_slots)
     tickets = []
     for c, rho, e, n_c in qs:
         tickets.append(m.mdeos_serve_submit(ctx, c, rho, e, n_c, m.mdeos_serve_now(ctx)))
@@ -243,5 +243,27 @@ def test_stop_without_drain_while_chunks_run():
                 r = got[tk_c[j]]
                 assert r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) == 0
                 assert r.tobytes() == ref[j].tobytes(), (c, j)
+    finally:
+        m.mdeos_destroy(ctx)
+
+
+def test_slot_cap_limits_cells_per_chunk():
+    """With at most two cells advancing at once, six cells of one cold
+    (200-step) and one warm (100-step) query each need 36 cell-chunks of 50
+    steps, so at least 18 chunks; every result is bitwise that of the cell
+    alone."""
+    ctx = m.mdeos_create()
+    try:
+        qs = queries(n_cells=6, per_cell=2, seed=11)
+        tickets, got, stats = serve_all(ctx, qs, 50, max_slots=2)
+        print(f"  slot cap 2: {stats['chunks']} chunks", flush=True)
+        assert len(got) == len(qs), stats
+        assert stats["chunks"] >= 18, stats
+        for c in range(6):
+            seq = [q for q in qs if q[0] == c]
+            tk = [t for t, q in zip(tickets, qs) if q[0] == c]
+            ref = alone(ctx, c, seq)
+            for k in range(len(seq)):
+                assert got[tk[k]].tobytes() == ref[k].tobytes(), (c, k)
     finally:
         m.mdeos_destroy(ctx)

@@ -75,6 +75,36 @@ def test_minimum_image_box_forces(ctx, rho, rc):
         assert abs(Ug[k] - ref.U[k]) <= 1e-6 * den and abs(K[k] - ref.K[k]) <= 1e-6 * den, k
 
 
+def test_uniform_batch_full_size():
+    """The uniform batch at full size (4096 cells of 500 atoms, 2000 steps) in
+    the launch configuration the bench times (autotuned shapes, default
+    skin): the oracle on the stratified sample of 64 cells (one per density
+    and temperature bin) at the statistical bar, and eight of those cells run
+    again as a batch of their own, bitwise equal to their results in the full
+    batch."""
+    w = wl.cfg2()
+    specs, sch = m.specs_from_workload(w)
+    tctx = m.mdeos_create(autotune=1)
+    try:
+        print("uniform batch of 4096", flush=True)
+        res = m.mdeos_eval_batch(tctx, specs, sch)
+        bad = (res["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)) != 0
+        assert not bad.any(), np.nonzero(bad)
+        assert (res["n_samples"] == w.sched.n_avg).all()
+        pick = wl.stratified_sample(w)
+        assert len(pick) >= 48, len(pick)
+        sub = pick[:: max(1, len(pick) // 8)][:8]
+        s2, _ = m.specs_from_workload(w.subset(sub))
+        again = m.mdeos_eval_batch(tctx, s2, sch)
+        for k, i in enumerate(sub):
+            assert again[k].tobytes() == res[i].tobytes(), i
+    finally:
+        m.mdeos_destroy(tctx)
+    o = oracle_many([ocell(w, i) for i in pick], w.sched)
+    check_stats([res[i] for i in pick], o, "uniform",
+                [f"cell {i} rho {w.rho[i]:.3f} T {w.T[i]:.2f}" for i in pick])
+
+
 def test_uneven_batch_full_size(ctx):
     """All 10,000 uneven cells in one eval_batch; oracle on two cells per
     (N, rc) bucket for every size up to 2048 atoms (the 2048-atom oracle cells

@@ -267,3 +267,53 @@ def test_slot_cap_limits_cells_per_chunk():
                 assert got[tk[k]].tobytes() == ref[k].tobytes(), (c, k)
     finally:
         m.mdeos_destroy(ctx)
+
+
+def test_cfg4_stream_served_equal_alone_on_sampled_cells():
+    """The serving stream at its full mesh (128 x 128 cells of 256, 500 or
+    864 atoms; cold lifts of 2000 steps, then warm starts of 500) for two
+    continuum steps, submitted at 50,000 queries/s, above what the device
+    sustains, so tens of thousands of queries mix in the chunks. Eight
+    sampled cells, run alone through lift / advance / warm start / restrict,
+    give the same bits as served."""
+    queries, meta = wl.cfg4_queries(50_000.0, mesh=128, t_max=2)
+    cold, warm = meta["cold"], meta["warm"]
+    sc = m.make_schedule(cold.n_steps, cold.n_avg, cold.rescale_steps)
+    sw = m.make_schedule(warm.n_steps, warm.n_avg, warm.rescale_steps)
+    rc, dt, seed = meta["rc"], meta["dt"], wl.DEFAULT_SEED
+    ctx = m.mdeos_create()
+    try:
+        print(f"cfg4 stream: {len(queries)} queries", flush=True)
+        m.mdeos_serve_start(ctx, sc, sw, rc, dt, seed, chunk_steps=100)
+        t0 = m.mdeos_serve_now(ctx)
+        ticket_of = {}
+        for q in queries:
+            while m.mdeos_serve_now(ctx) - t0 < q.t_arrival:
+                time.sleep(0.0002)
+            ticket_of[(q.cell, q.step)] = m.mdeos_serve_submit(ctx, q.cell, q.rho, q.e, q.n_c, m.mdeos_serve_now(ctx))
+        m.mdeos_serve_stop(ctx, drain=True)
+        tk, res, _ = m.mdeos_serve_poll(ctx, 1 << 16)
+        stats = m.mdeos_serve_stats_get(ctx)
+        got = {int(k): r for k, r in zip(tk, res)}
+        print(f"  served {len(got)} in {stats['chunks']} chunks", flush=True)
+        assert len(got) == len(queries)
+        assert not any(r["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW) for r in got.values())
+        sizes = meta["sizes"]
+        pick = [int(np.nonzero(sizes == n)[0][j]) for n in (256, 500, 864) for j in (0, 7, 31)][:8]
+        by_cell = {}
+        for q in queries:
+            by_cell.setdefault(q.cell, []).append(q)
+        for c in pick:
+            seq = sorted(by_cell[c], key=lambda q: q.step)
+            h = m.mdeos_lift(ctx, m.make_specs(seq[0].rho, seq[0].e, seq[0].n_c, rc, dt, seed, c), sc)
+            m.mdeos_advance(ctx, h, 10 ** 6)
+            ref = [m.mdeos_restrict(ctx, h)[0]]
+            for q in seq[1:]:
+                m.mdeos_warm_start(ctx, h, q.rho, q.e, sw)
+                m.mdeos_advance(ctx, h, 10 ** 6)
+                ref.append(m.mdeos_restrict(ctx, h)[0])
+            m.mdeos_release(ctx, h)
+            for q, r in zip(seq, ref):
+                assert got[ticket_of[(c, q.step)]].tobytes() == r.tobytes(), (c, q.step)
+    finally:
+        m.mdeos_destroy(ctx)

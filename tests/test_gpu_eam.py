@@ -250,3 +250,46 @@ def test_langevin_minimum_image_4000_first_20_steps(ctx):
     uerr, kerr = np.abs(U - ref.U) / den, np.abs(K - ref.K) / den
     print(f"  max rel err: F {ferr.max():.2e} U {uerr.max():.2e} K {kerr.max():.2e}", flush=True)
     assert ferr.max() <= F_TOL and uerr.max() <= E_TOL and kerr.max() <= E_TOL
+
+
+def test_eam_batch_full_size():
+    """The embedded-atom batch at full size (4096 cells of 500 atoms, 2000
+    steps) in the launch configuration the bench times (autotuned shapes,
+    skin 0.5, inner lists at rc + 0.12): the oracle on the stratified sample
+    of up to 64 cells at the statistical bar, and eight of those cells run
+    again as a batch of their own, bitwise equal to their full-batch results."""
+    from _stats import check_stats, oracle_many
+    w = wl.eam_cu()
+    specs, sch = m.specs_from_workload(w)
+    tctx = m.mdeos_create(autotune=1, potential=m.POT_EAM, skin=0.5, prune_skin=0.12)
+    try:
+        print("eam batch of 4096", flush=True)
+        res = m.mdeos_eval_batch(tctx, specs, sch)
+        bad = (res["status"] & (m.CELL_NONFINITE | m.CELL_OVERFLOW)) != 0
+        assert not bad.any(), np.nonzero(bad)
+        assert (res["n_samples"] == w.sched.n_avg).all()
+        pick = wl.stratified_sample(w)
+        assert len(pick) >= 48, len(pick)
+        sub = pick[:: max(1, len(pick) // 8)][:8]
+        s2, _ = m.specs_from_workload(w.subset(sub))
+        again = m.mdeos_eval_batch(tctx, s2, sch)
+        for k, i in enumerate(sub):
+            assert again[k].tobytes() == res[i].tobytes(), i
+    finally:
+        m.mdeos_destroy(tctx)
+    cells = [oracle.Cell(rho=float(w.rho[i]), e=float(w.e[i]), n_c=5, rc=1.5, dt=0.001, seed=int(w.seed),
+                         cell_id=int(w.cell_id[i]), potential=1, eam_c=C_SC) for i in pick]
+    s = w.sched
+    o = oracle_many(cells, s.n_steps, s.n_avg, s.rescale_steps)
+    # E_cold of a compressed lattice is a large repulsive pair sum less a large
+    # embedding term (at rho 5.9: +452 and -595 per atom, net -143). FP32 pair
+    # terms carry a relative error of order 1e-7 each, and on a lattice the
+    # pairs of one shell share it, so the bar is 1e-6 of the two magnitudes.
+    bar = []
+    for c in cells:
+        x = oracle.lattice(c.n_c, c.rho)
+        _, U, _, _, rb = oracle.forces_eam(x, oracle.box_length(c.n_c, c.rho), c.rc, c.eam_c)
+        emb = -c.eam_c * np.sqrt(rb).sum()
+        bar.append(1e-6 * (abs(U - emb) + abs(emb)) / len(x))
+    check_stats([res[i] for i in pick], o, "eam", [f"cell {i} rho {w.rho[i]:.3f} T {w.T[i]:.1f}" for i in pick],
+                ecold_abs=bar)

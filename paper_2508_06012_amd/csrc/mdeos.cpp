@@ -364,6 +364,7 @@ Ctx::~Ctx() {
   hipSetDevice(device);
   hipDeviceSynchronize();
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second.exec);
+  for (hipGraphExec_t e : retired_graphs) hipGraphExecDestroy(e);
   for (void* p : arena_ptrs) hipFree(p);
   hipFree(d_cells);
   hipFree(d_counters);
@@ -503,8 +504,14 @@ mdeos_status Ctx::stage_wait() {
   return MDEOS_OK;
 }
 
+// Empties the graph cache. An executable graph leaves the cache here but is
+// destroyed only at the next clear, so none is destroyed right after its last
+// launch completed (clears follow a device synchronization, and the serving
+// loop keeps a launch in flight while it prepares the next one).
 void Ctx::graphs_clear() {
-  for (auto& kv : graphs) hipGraphExecDestroy(kv.second.exec);
+  for (hipGraphExec_t e : retired_graphs) hipGraphExecDestroy(e);
+  retired_graphs.clear();
+  for (auto& kv : graphs) retired_graphs.push_back(kv.second.exec);
   graphs.clear();
 }
 
@@ -970,7 +977,10 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
   }
   auto it = graphs.find(key);
   if (it == graphs.end()) {
-    if (graphs.size() > 256) graphs_clear();
+    if (graphs.size() > 256) {
+      HCHECK(hipStreamSynchronize(s));
+      graphs_clear();
+    }
     hipGraph_t g;
     HCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_all(s);

@@ -176,6 +176,7 @@ struct Ctx {
   bool work_inflight = false;
 
   std::map<std::string, GraphEntry> graphs;
+  std::vector<hipGraphExec_t> retired_graphs;  // cleared from the cache, destroyed at the next clear
   std::map<std::string, Variant> tuned;
   Variant forced_variant{0, 0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe,mi" (tuning)
   bool tune_log = false;  // MDEOS_TUNE_LOG=1: the autotuner prints each candidate's timings to stderr

@@ -977,10 +977,10 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
   }
   auto it = graphs.find(key);
   if (it == graphs.end()) {
-    if (graphs.size() > 256) {
-      HCHECK(hipStreamSynchronize(s));
-      graphs_clear();
-    }
+    // a new graph is captured on an idle stream (a miss is rare once a batch
+    // or serving composition has settled, so the wait costs little)
+    HCHECK(hipStreamSynchronize(s));
+    if (graphs.size() > 256) graphs_clear();
     hipGraph_t g;
     HCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_all(s);

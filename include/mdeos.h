@@ -334,7 +334,7 @@ typedef struct {
     long long submitted, completed, cold, warm, relifts, evictions;
     long long chunks;          /* scheduling rounds launched */
     long long queued;          /* queries waiting now */
-    long long active;          /* cells admitted and not yet answered */
+    long long active;          /* cells advancing now */
     long long resident;        /* cells with resident state now */
     size_t resident_bytes;     /* device bytes of resident state */
     double atom_steps;         /* MD atom-steps executed */

@@ -335,8 +335,6 @@ mdeos_status Ctx::init(const mdeos_config* cfg) {
     HCHECK(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming));
   }
   HCHECK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-  HCHECK(hipEventCreateWithFlags(&ev_stage, hipEventDisableTiming));
-  HCHECK(hipEventCreateWithFlags(&ev_work, hipEventDisableTiming));
   HCHECK(hipEventCreate(&ev_t0));
   HCHECK(hipEventCreate(&ev_t1));
   if (init_kernel_attributes() != hipSuccess) {
@@ -364,7 +362,6 @@ Ctx::~Ctx() {
   hipSetDevice(device);
   hipDeviceSynchronize();
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second.exec);
-  for (hipGraphExec_t e : retired_graphs) hipGraphExecDestroy(e);
   for (void* p : arena_ptrs) hipFree(p);
   hipFree(d_cells);
   hipFree(d_counters);
@@ -374,9 +371,6 @@ Ctx::~Ctx() {
   hipFree(d_idx);
   hipHostFree(h_stage);
   hipHostFree(h_results);
-  hipHostFree(h_launch_work);
-  if (ev_stage) hipEventDestroy(ev_stage);
-  if (ev_work) hipEventDestroy(ev_work);
   if (own_stream) hipStreamDestroy(own_stream);
   for (int i = 0; i < kAux; ++i) {
     if (aux[i]) hipStreamDestroy(aux[i]);
@@ -484,7 +478,6 @@ mdeos_status Ctx::ensure_scratch(size_t work_n, size_t counters_n, size_t gl_byt
 mdeos_status Ctx::ensure_stage(size_t bytes) {
   if (bytes <= stage_cap) return MDEOS_OK;
   HCHECK(hipDeviceSynchronize());
-  stage_inflight = false;
   hipHostFree(h_stage);
   h_stage = nullptr;
   size_t nb = std::max(bytes, stage_cap * 2);
@@ -496,22 +489,8 @@ mdeos_status Ctx::ensure_stage(size_t bytes) {
   return MDEOS_OK;
 }
 
-// Waits for the copies still reading the staging buffer (issued on any
-// stream); the buffer may be rewritten afterwards.
-mdeos_status Ctx::stage_wait() {
-  if (stage_inflight) HCHECK(hipEventSynchronize(ev_stage));
-  stage_inflight = false;
-  return MDEOS_OK;
-}
-
-// Empties the graph cache. An executable graph leaves the cache here but is
-// destroyed only at the next clear, so none is destroyed right after its last
-// launch completed (clears follow a device synchronization, and the serving
-// loop keeps a launch in flight while it prepares the next one).
 void Ctx::graphs_clear() {
-  for (hipGraphExec_t e : retired_graphs) hipGraphExecDestroy(e);
-  retired_graphs.clear();
-  for (auto& kv : graphs) retired_graphs.push_back(kv.second.exec);
+  for (auto& kv : graphs) hipGraphExecDestroy(kv.second.exec);
   graphs.clear();
 }
 
@@ -618,9 +597,8 @@ mdeos_status Ctx::upload_records(const std::vector<int>& idx, hipStream_t s) {
   std::sort(sorted.begin(), sorted.end());
   mdeos_status st = ensure_stage(sizeof(CellRec) * sorted.size());
   if (st != MDEOS_OK) return st;
-  // wait for earlier copies out of the staging buffer only: work already
-  // queued on the stream (a running chunk) keeps running meanwhile
-  if ((st = stage_wait()) != MDEOS_OK) return st;
+  // wait for earlier uses of the staging buffer
+  HCHECK(hipStreamSynchronize(s));
   CellRec* stage = (CellRec*)h_stage;
   size_t i = 0;
   size_t k = 0;
@@ -632,8 +610,6 @@ mdeos_status Ctx::upload_records(const std::vector<int>& idx, hipStream_t s) {
     k += j - i + 1;
     i = j + 1;
   }
-  HCHECK(hipEventRecord(ev_stage, s));
-  stage_inflight = true;
   return MDEOS_OK;
 }
 
@@ -884,29 +860,11 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
   }
   mdeos_status st = ensure_scratch(work_n, kMaxBuckets, gl_bytes, 1);
   if (st != MDEOS_OK) return st;
-  // The work lists go up from pinned memory, so the copy is queued behind
-  // the work already on the stream instead of blocking the host until it
-  // ends (a copy from pageable memory is synchronous); only the previous
-  // copy out of the buffer must have ended before it is rewritten.
-  if (work_inflight) HCHECK(hipEventSynchronize(ev_work));
-  work_inflight = false;
-  if (work_n > h_launch_work_cap) {
-    hipHostFree(h_launch_work);
-    h_launch_work = nullptr;
-    const size_t nc = std::max(work_n, h_launch_work_cap * 2);
-    if (hipHostMalloc((void**)&h_launch_work, sizeof(int) * nc, hipHostMallocDefault) != hipSuccess) {
-      h_launch_work_cap = 0;
-      set_error("hipHostMalloc failed");
-      return MDEOS_OUT_OF_MEMORY;
-    }
-    h_launch_work_cap = nc;
-  }
-  int* host_work = h_launch_work;
-  std::fill(host_work, host_work + work_n, 0);
+  std::vector<int> host_work(work_n, 0);
   for (size_t i = 0; i < buckets.size(); ++i) {
     host_work[2 * i] = (int)buckets[i].cells.size();
     host_work[2 * i + 1] = buckets[i].work_off;
-    std::copy(buckets[i].cells.begin(), buckets[i].cells.end(), host_work + buckets[i].work_off);
+    std::copy(buckets[i].cells.begin(), buckets[i].cells.end(), host_work.begin() + buckets[i].work_off);
   }
   char hdr[96];
   snprintf(hdr, sizeof(hdr), "%d|%p|", step_budget, (void*)s);
@@ -917,9 +875,7 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
              b.v.ext, b.v.list_lds, b.v.wpe, b.caps.list_cap, b.caps.ncell_cap, b.caps.n_pad, b.grid, b.lds, b.gl_off);
     key += bb;
   }
-  HCHECK(hipMemcpyAsync(d_work, host_work, sizeof(int) * work_n, hipMemcpyHostToDevice, s));
-  HCHECK(hipEventRecord(ev_work, s));
-  work_inflight = true;
+  HCHECK(hipMemcpyAsync(d_work, host_work.data(), sizeof(int) * host_work.size(), hipMemcpyHostToDevice, s));
 
   auto launch_all = [&](hipStream_t ms) -> hipError_t {
     hipError_t e = launch_zero_ints(d_counters, (int)buckets.size(), ms);
@@ -977,9 +933,6 @@ mdeos_status Ctx::run_buckets(std::vector<Bucket>& buckets, int step_budget, hip
   }
   auto it = graphs.find(key);
   if (it == graphs.end()) {
-    // a new graph is captured on an idle stream (a miss is rare once a batch
-    // or serving composition has settled, so the wait costs little)
-    HCHECK(hipStreamSynchronize(s));
     if (graphs.size() > 256) graphs_clear();
     hipGraph_t g;
     HCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1010,22 +963,6 @@ mdeos_status Ctx::restrict_cells(const std::vector<int>& idx, mdeos_result* out,
   HCHECK(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
   HCHECK(launch_restrict(d_cells, d_idx, n, d_results, s));
   return fetch_results(n, out, s);
-}
-
-// Queues the restricting operator over the given slots and the copy of its
-// results into h_out (pinned, n entries), without waiting: the caller waits
-// on an event recorded after this call before reading h_out. h_idx (pinned,
-// n entries) stages the slot list and must not be rewritten before then.
-mdeos_status Ctx::restrict_async(const std::vector<int>& idx, int* h_idx, DevResult* h_out, hipStream_t s) {
-  const int n = (int)idx.size();
-  if (n == 0) return MDEOS_OK;
-  mdeos_status st = ensure_scratch(2 * kMaxBuckets, kMaxBuckets, 0, n);
-  if (st != MDEOS_OK) return st;
-  std::copy(idx.begin(), idx.end(), h_idx);
-  HCHECK(hipMemcpyAsync(d_idx, h_idx, sizeof(int) * n, hipMemcpyHostToDevice, s));
-  HCHECK(launch_restrict(d_cells, d_idx, n, d_results, s));
-  HCHECK(hipMemcpyAsync(h_out, d_results, sizeof(DevResult) * n, hipMemcpyDeviceToHost, s));
-  return MDEOS_OK;
 }
 
 AdvanceParams Ctx::make_params(const Bucket& b, int bi, int step_budget) {
@@ -1145,7 +1082,6 @@ mdeos_status Ctx::upload_state(int slot, const double* xyz, const double* v, hip
   const int N = r.N;
   mdeos_status st = ensure_stage(sizeof(double) * 6 * N);
   if (st != MDEOS_OK) return st;
-  if ((st = stage_wait()) != MDEOS_OK) return st;
   HCHECK(hipStreamSynchronize(s));
   double* f = (double*)h_stage;
   const double L = r.Lw;

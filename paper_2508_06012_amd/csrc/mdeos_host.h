@@ -168,15 +168,8 @@ struct Ctx {
   size_t h_results_cap = 0;
   unsigned char* h_stage = nullptr;
   size_t stage_cap = 0;
-  hipEvent_t ev_stage = nullptr;  // recorded after the last copy that reads h_stage
-  bool stage_inflight = false;
-  int* h_launch_work = nullptr;  // pinned copy of the launch work lists
-  size_t h_launch_work_cap = 0;
-  hipEvent_t ev_work = nullptr;  // recorded after the last copy that reads h_launch_work
-  bool work_inflight = false;
 
   std::map<std::string, GraphEntry> graphs;
-  std::vector<hipGraphExec_t> retired_graphs;  // cleared from the cache, destroyed at the next clear
   std::map<std::string, Variant> tuned;
   Variant forced_variant{0, 0, 0, 0, 0, 0};  // MDEOS_FORCE_VARIANT="block,apt,ext,lds,wpe,mi" (tuning)
   bool tune_log = false;  // MDEOS_TUNE_LOG=1: the autotuner prints each candidate's timings to stderr
@@ -207,7 +200,6 @@ struct Ctx {
   mdeos_status ensure_cells(int need);
   mdeos_status ensure_scratch(size_t work_n, size_t counters_n, size_t gl_bytes, size_t res_n);
   mdeos_status ensure_stage(size_t bytes);
-  mdeos_status stage_wait();
   void graphs_clear();
 
   void fill_record(CellRec& r, const mdeos_cell_spec& s, const mdeos_schedule& q, const CellPlan& p, int atom_off);
@@ -229,7 +221,6 @@ struct Ctx {
   int timed_launches = 0;
   mdeos_status run_buckets(std::vector<Bucket>& buckets, int step_budget, hipStream_t s, bool use_graph);
   mdeos_status restrict_cells(const std::vector<int>& idx, mdeos_result* out, hipStream_t s);
-  mdeos_status restrict_async(const std::vector<int>& idx, int* h_idx, DevResult* h_out, hipStream_t s);
   AdvanceParams make_params(const Bucket& b, int bi, int step_budget);
   mdeos_status fetch_results(int n, mdeos_result* out, hipStream_t s);
   mdeos_status eval(int n, const mdeos_cell_spec* specs, const mdeos_schedule* sched, mdeos_result* out,

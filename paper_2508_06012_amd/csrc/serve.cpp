@@ -214,28 +214,6 @@ void Ctx::serve_loop() {
   long long round = 0;
   size_t resident_bytes = 0;
   long long resident = 0;
-  // Rounds overlap: round r's chunk and the restriction of the cells it
-  // finishes are queued behind round r-1's, whose results the host delivers
-  // (after its event) while round r runs, so the device never waits for the
-  // host between chunks. Two pinned banks hold the slot lists and results of
-  // the two rounds in flight.
-  struct Round {
-    bool live = false;
-    int bank = 0;
-    std::vector<Active> done;  // the cells the chunk finishes, in restriction order
-    double atom_steps = 0.0;
-  };
-  Round prev;
-  long long launches = 0;
-  int* h_idx[2] = {nullptr, nullptr};
-  DevResult* h_res[2] = {nullptr, nullptr};
-  size_t bank_cap[2] = {0, 0};
-  hipEvent_t ev_round[2] = {nullptr, nullptr};
-  for (int k = 0; k < 2; ++k)
-    if (hipEventCreateWithFlags(&ev_round[k], hipEventDisableTiming) != hipSuccess) {
-      fprintf(stderr, "mdeos serve: hipEventCreate failed\n");
-      return;
-    }
 
   auto finish_all = [&](bool drop) {
     if (drop) waiting.clear();
@@ -245,8 +223,7 @@ void Ctx::serve_loop() {
     bool stop = false, drain = true;
     {
       std::unique_lock<std::mutex> lk(serve_mu);
-      if (active.empty() && pending.empty() && !prev.live && waiting.empty() && serve_queue.empty() &&
-          !serve_stop_flag)
+      if (active.empty() && pending.empty() && waiting.empty() && serve_queue.empty() && !serve_stop_flag)
         serve_cv.wait_for(lk, std::chrono::milliseconds(2));
       while (!serve_queue.empty()) {
         waiting.push_back(serve_queue.front());
@@ -257,8 +234,8 @@ void Ctx::serve_loop() {
       serve_stats.queued = (long long)waiting.size();
     }
     if (stop && !drain) finish_all(true);
-    if (stop && waiting.empty() && active.empty() && pending.empty() && !prev.live) break;
-    if (stop && !drain && active.empty() && pending.empty() && !prev.live) break;
+    if (stop && waiting.empty() && active.empty() && pending.empty()) break;
+    if (stop && !drain && active.empty() && pending.empty()) break;
 
     std::lock_guard<std::recursive_mutex> g(mu);
     ++round;
@@ -310,6 +287,7 @@ void Ctx::serve_loop() {
             resident -= 1;
             free_cells({vc.slot});
             vc.slot = -1;
+            std::lock_guard<std::mutex> lk(serve_mu);
             serve_stats.evictions += 1;
           }
           if (resident_bytes + need > hbm_budget) break;  // wait for capacity
@@ -352,86 +330,21 @@ void Ctx::serve_loop() {
       break;
     }
     active.insert(active.end(), fresh.begin(), fresh.end());
+    if (active.empty()) continue;
 
-    // ---- one chunk for every admitted cell, then the restriction of the
-    // cells it finishes; both are queued behind the previous round's work
-    Round cur;
-    if (!active.empty()) {
-      std::vector<int> slots_now;
-      slots_now.reserve(active.size());
-      for (const Active& a : active) slots_now.push_back(a.slot);
-      std::vector<Bucket> b;
-      make_buckets(slots_now, b, cfg.chunk_steps, true);
-      if (run_buckets(b, cfg.chunk_steps, s, true) != MDEOS_OK) {
-        fprintf(stderr, "mdeos serve: launch failed: %s\n", mdeos_last_error());
-        break;
-      }
-      // the cells this chunk finishes leave the active set now, so the next
-      // chunk (queued before this one ends) no longer advances them
-      size_t w = 0;
-      for (size_t i = 0; i < active.size(); ++i) {
-        Active a = active[i];
-        const int adv = std::min(cfg.chunk_steps, a.n_steps - a.step);
-        a.step += adv;
-        cur.atom_steps += (double)adv * h_cells[a.slot].N;
-        if (a.step >= a.n_steps) cur.done.push_back(a);
-        else active[w++] = a;
-      }
-      active.resize(w);
-      const int bk = (int)(launches & 1);  // the bank of two launches ago, whose results were read
-      if (cur.done.size() > bank_cap[bk]) {
-        hipHostFree(h_idx[bk]);
-        hipHostFree(h_res[bk]);
-        h_idx[bk] = nullptr;
-        h_res[bk] = nullptr;
-        bank_cap[bk] = 0;
-        const size_t nc = std::max(cur.done.size(), (size_t)256);
-        if (hipHostMalloc((void**)&h_idx[bk], sizeof(int) * nc, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&h_res[bk], sizeof(DevResult) * nc, hipHostMallocDefault) != hipSuccess) {
-          fprintf(stderr, "mdeos serve: hipHostMalloc of the result bank failed\n");
-          break;
-        }
-        bank_cap[bk] = nc;
-      }
-      std::vector<int> fin;
-      fin.reserve(cur.done.size());
-      for (const Active& a : cur.done) fin.push_back(a.slot);
-      if (!fin.empty() && restrict_async(fin, h_idx[bk], h_res[bk], s) != MDEOS_OK) {
-        fprintf(stderr, "mdeos serve: restrict failed: %s\n", mdeos_last_error());
-        break;
-      }
-      if (hipEventRecord(ev_round[bk], s) != hipSuccess) break;
-      cur.bank = bk;
-      cur.live = true;
-      ++launches;
+    // ---- one chunk for every admitted cell ------------------------------
+    std::vector<int> slots_now;
+    slots_now.reserve(active.size());
+    for (const Active& a : active) slots_now.push_back(a.slot);
+    std::vector<Bucket> b;
+    make_buckets(slots_now, b, cfg.chunk_steps, true);
+    if (run_buckets(b, cfg.chunk_steps, s, true) != MDEOS_OK) {
+      fprintf(stderr, "mdeos serve: launch failed: %s\n", mdeos_last_error());
+      break;
     }
-
-    // ---- the previous round ends on the device while this one is queued:
-    // deliver its results
-    if (prev.live) {
-      if (hipEventSynchronize(ev_round[prev.bank]) != hipSuccess) {
-        fprintf(stderr, "mdeos serve: device error\n");
-        break;
-      }
-      const double t_done = mono_now() - serve_t0;
-      std::lock_guard<std::mutex> lk(serve_mu);
-      serve_stats.chunks += 1;
-      serve_stats.atom_steps += prev.atom_steps;
-      for (size_t k = 0; k < prev.done.size(); ++k) {
-        const Active& a = prev.done[k];
-        ServeDone d{a.ticket, {}, t_done};
-        static_assert(sizeof(DevResult) == sizeof(mdeos_result), "result layout");
-        memcpy(&d.res, &h_res[prev.bank][k], sizeof(mdeos_result));
-        if (d.res.status & MDEOS_CELL_COLD_RELIFT) serve_stats.relifts += 1;
-        serve_done.push_back(d);
-        serve_stats.completed += 1;
-        serve_cells[a.cell_id].busy = false;
-      }
-    }
-    prev = std::move(cur);
-
-    // ---- while the queued chunk runs: take the queries that arrived
-    // meanwhile and plan their admission; they join the next chunk
+    // while the chunk runs: take the queries that arrived meanwhile and plan
+    // their admission (host work that would otherwise leave the device idle
+    // between chunks); they join the next chunk
     {
       std::lock_guard<std::mutex> lk(serve_mu);
       while (!serve_queue.empty()) {
@@ -441,20 +354,60 @@ void Ctx::serve_loop() {
       serve_stats.queued = (long long)waiting.size();
     }
     admit(pending);
+    double atom_steps = 0.0;
+    std::vector<int> finished;
+    std::vector<size_t> fin_pos;
+    for (size_t i = 0; i < active.size(); ++i) {
+      Active& a = active[i];
+      const int adv = std::min(cfg.chunk_steps, a.n_steps - a.step);
+      a.step += adv;
+      atom_steps += (double)adv * h_cells[a.slot].N;
+      if (a.step >= a.n_steps) {
+        finished.push_back(a.slot);
+        fin_pos.push_back(i);
+      }
+    }
+    std::vector<mdeos_result> res(finished.size());
+    if (!finished.empty()) {
+      if (restrict_cells(finished, res.data(), s) != MDEOS_OK) {
+        fprintf(stderr, "mdeos serve: restrict failed: %s\n", mdeos_last_error());
+        break;
+      }
+    } else if (hipStreamSynchronize(s) != hipSuccess) {
+      break;
+    }
+    const double t_done = mono_now() - serve_t0;
     {
       std::lock_guard<std::mutex> lk(serve_mu);
-      serve_stats.active = (long long)(active.size() + pending.size() + prev.done.size());
+      serve_stats.chunks += 1;
+      serve_stats.atom_steps += atom_steps;
+      for (size_t k = 0; k < finished.size(); ++k) {
+        const Active& a = active[fin_pos[k]];
+        ServeDone d{a.ticket, res[k], t_done};
+        if (res[k].status & MDEOS_CELL_COLD_RELIFT) serve_stats.relifts += 1;
+        serve_done.push_back(d);
+        serve_stats.completed += 1;
+        serve_cells[a.cell_id].busy = false;
+      }
+    }
+    // drop finished entries (positions ascending) in one pass, keeping the order
+    {
+      size_t w = 0, f = 0;
+      for (size_t i = 0; i < active.size(); ++i) {
+        if (f < fin_pos.size() && fin_pos[f] == i) {
+          ++f;
+          continue;
+        }
+        active[w++] = active[i];
+      }
+      active.resize(w);
+    }
+    {
+      std::lock_guard<std::mutex> lk(serve_mu);
+      serve_stats.active = (long long)active.size();
       serve_stats.resident = resident;
       serve_stats.resident_bytes = resident_bytes;
     }
-  }
-  // the device may still hold the last round (after an error): let it end
-  // before its result banks go
-  (void)hipStreamSynchronize(s);
-  for (int k = 0; k < 2; ++k) {
-    hipHostFree(h_idx[k]);
-    hipHostFree(h_res[k]);
-    if (ev_round[k]) hipEventDestroy(ev_round[k]);
   }
   std::lock_guard<std::mutex> lk(serve_mu);
   serve_stats.active = 0;

@@ -211,7 +211,7 @@ def test_restart_releases_the_last_sessions_resident_cells():
 
 
 def test_stop_without_drain_while_chunks_run():
-    """Stopping without draining while chunks are queued on the device: the
+    """Stopping without draining while chunks run on the device: the
     queries not yet admitted are dropped, the admitted ones finish, and every
     delivered result is bitwise that of its cell's query prefix run alone."""
     ctx = m.mdeos_create()

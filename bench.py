@@ -206,6 +206,24 @@ def serve_leg(m, wl, rate: float, mesh: int, t_steps: int, seconds_cap: float):
     return out
 
 
+def serve_leg_child(rate: float, t_steps: int) -> dict:
+    """One serving leg in a child process of its own, so that a leg that
+    fails is reported in the JSON line (with its exit status) instead of ending
+    the whole bench."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serve-leg", str(rate), str(t_steps)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    except subprocess.TimeoutExpired:
+        return {"rate_qps": rate, "continuum_steps": t_steps, "error": "timed out after 300 s"}
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode == 0 and lines:
+        return json.loads(lines[-1])
+    tail = " | ".join(ln for ln in r.stderr.strip().splitlines()[-3:] if "amdgpu.ids" not in ln)
+    why = f"signal {-r.returncode}" if r.returncode < 0 else f"exit status {r.returncode}"
+    return {"rate_qps": rate, "continuum_steps": t_steps, "error": f"{why}: {tail}"}
+
+
 def plain_latency(m, wl):
     """Per-eval latency of the plain path (one cell per launch) for the
     serving stream's cell sizes: a fresh lift + the cold schedule (2000
@@ -438,6 +456,9 @@ def main() -> int:
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-leg", nargs=2, type=float, metavar=("RATE", "STEPS"),
+                    help="run one serving leg of the default run and print its JSON line (the default run "
+                         "starts each leg as a child process of its own)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="end with one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
@@ -454,6 +475,12 @@ def main() -> int:
 
     if args.valu_pass:
         print(" ".join(VALU_PASSES[args.valu_pass - 1]))
+        return 0
+    if args.serve_leg:
+        from paper_2508_06012_amd import mdeos as m
+        from paper_2508_06012_amd import workloads as wl
+        rate, t_steps = args.serve_leg
+        print(json.dumps(serve_leg(m, wl, rate, mesh=128, t_steps=int(t_steps), seconds_cap=25.0)), flush=True)
         return 0
     if args.trace_summary or args.pmc_summary or args.valu_summary:
         if args.trace_summary:
@@ -585,7 +612,7 @@ def main() -> int:
         for rate, t_steps in SERVE_LEGS:
             print(f"# serving leg: 128 x 128 mesh, {rate:.0f} queries/s, {t_steps} continuum steps", file=sys.stderr,
                   flush=True)
-            legs.append(serve_leg(m, wl, rate, mesh=128, t_steps=t_steps, seconds_cap=25.0))
+            legs.append(serve_leg_child(rate, t_steps))
             print(f"#   {json.dumps(legs[-1])}", file=sys.stderr, flush=True)
         out["serving"] = {"workload": "cfg4-serving-128x128", "legs": legs, "plain_latency": plain_latency(m, wl)}
     if default and not args.no_cpu:

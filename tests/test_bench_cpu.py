@@ -65,3 +65,13 @@ def test_multi_gpu_request_exits_with_message(capsys, monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
     assert bench.main() == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_failed_serving_leg_is_reported_not_fatal(monkeypatch):
+    """A serving leg runs in a child process; when it fails (here: no device
+    in this process's environment), the leg comes back as an error entry with
+    the child's exit status, and the caller goes on."""
+    monkeypatch.setenv("HIP_VISIBLE_DEVICES", "-1")  # the child sees no device, on any host
+    leg = bench.serve_leg_child(2000.0, 1)
+    assert leg["rate_qps"] == 2000.0 and leg["continuum_steps"] == 1
+    assert "error" in leg and ("exit status" in leg["error"] or "signal" in leg["error"]), leg
